@@ -1,0 +1,215 @@
+"""Benchmark: Gcell-updates/s and achieved HBM GB/s of the split Euler step.
+
+Workload: 512^3 cells, smooth periodic initial state (seeded Fourier fields),
+FP32 storage and arithmetic (the headline), with the same run in FP64 for the
+FP32-vs-FP64 comparison.  One step = wave speeds (fused into the previous
+step's z sweep) -> dt -> x, y, z sweeps, i.e. one pass of the whole hot path.
+State buffers are resident in HBM before timing starts.
+
+Prints one JSON line.  `value` is Gcell-updates/s at FP32; `roofline` is the
+dominant sweep kernel's algorithmic bytes per launch over its mean launch
+duration, timed with HIP events around every launch inside the timed region;
+`cpu_baseline` times the FP64 CPU oracle on a bounded sample of the same
+workload on this host.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+CSRC = os.path.join(ROOT, "paper_2104_08571_amd", "csrc")
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(name.encode())
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources; else None."""
+    path = os.path.join(PROFILES, "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        data = json.load(f)
+    rec = data.get(f"{kernel}@{workload}")
+    if not rec or rec.get("source_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def run_gpu(n, dtype, layout, aosoa_w, steps, warmup, seed, tiling):
+    import torch
+
+    from paper_2104_08571_amd import initial_states as ist
+    from paper_2104_08571_amd import ripple_fv as R
+
+    ctx = R.ripple_fv_create(0)
+    stream = torch.cuda.current_stream().cuda_stream
+    g = R.make_grid((n, n, n), dtype=dtype, layout=layout, aosoa_w=aosoa_w,
+                    bc=(R.PERIODIC,) * 3, tiling=tiling)
+    a = torch.empty(g.bytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty(g.bytes, dtype=torch.uint8, device="cuda")
+    W = ist.smooth_periodic((n, n, n), seed=seed, device="cuda")
+    R.ripple_fv_import(ctx, g, W.data_ptr(), R.PRIMITIVE, a.data_ptr(), stream)
+    torch.cuda.synchronize()
+    del W
+    pa, pb = [a.data_ptr()], [b.data_ptr()]
+    if warmup > 0:
+        R.ripple_fv_run_batch(ctx, [g], pa, pb, warmup, 0.9, R.RUN_EAGER, stream)
+    torch.cuda.synchronize()
+    R.ripple_fv_profile(ctx)  # clear
+    # timed region: eager launches with HIP events around each kernel
+    t0 = time.perf_counter()
+    R.ripple_fv_run_batch(ctx, [g], pa, pb, steps, 0.9, R.RUN_PROFILE, stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = R.ripple_fv_profile(ctx)
+    # same loop replayed as captured hipGraphs
+    R.ripple_fv_run_batch(ctx, [g], pa, pb, 2, 0.9, R.RUN_GRAPH, stream)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    R.ripple_fv_run_batch(ctx, [g], pa, pb, steps, 0.9, R.RUN_GRAPH, stream)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    status = R.ripple_fv_check(ctx)
+    R.ripple_fv_destroy(ctx)
+    del a, b
+    torch.cuda.empty_cache()
+    return {"seconds": t1 - t0, "graph_seconds": t3 - t2, "profile": prof, "status": status}
+
+
+def cpu_baseline(n, seed, steps):
+    import numpy as np  # noqa: F401
+
+    from oracle import Oracle
+    from paper_2104_08571_amd import initial_states as ist
+
+    o = Oracle()
+    W = ist.smooth_periodic((n, n, n), seed=seed, device="cuda").cpu().numpy()
+    U = o.prim_to_cons(W)
+    del W
+    t0 = time.perf_counter()
+    o.run(U, steps, [1.0 / n] * 3, [1, 1, 1], cfl=0.9)
+    t1 = time.perf_counter()
+    cells = n ** 3
+    return {"value": cells * steps / (t1 - t0) / 1e9, "unit": "Gcell-updates/s",
+            "cores": o.num_threads(), "kind": "oracle",
+            "sample": f"{steps} step(s) of the {n}^3 FP64 smooth periodic workload "
+                      f"({t1 - t0:.1f} s on the host)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--layout", default="soa", choices=["soa", "aos", "aosoa16", "aosoa32", "aosoa64"])
+    ap.add_argument("--tiling", default="0,0,0,0",
+                    help="x_block,yz_block,yz_segment,persist (0 = defaults)")
+    ap.add_argument("--no-f64", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--cpu-steps", type=int, default=1,
+                    help="oracle steps timed for cpu_baseline (0 = skip)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the partitioned path is measured as sub-blocks on one GPU)", file=sys.stderr)
+        sys.exit(2)
+
+    from paper_2104_08571_amd import ripple_fv as R
+
+    lay = {"soa": (R.SOA, 0), "aos": (R.AOS, 0), "aosoa16": (R.AOSOA, 16),
+           "aosoa32": (R.AOSOA, 32), "aosoa64": (R.AOSOA, 64)}[args.layout]
+    tiling = tuple(int(v) for v in args.tiling.split(","))
+    n = args.n
+    cells = n ** 3
+    seed = 8571
+    workload = f"euler3d_smooth_periodic_{n}cubed"
+
+    def measure(dtype, s_bytes):
+        r = run_gpu(n, dtype, lay[0], lay[1], args.steps, args.warmup, seed, tiling)
+        secs = r["seconds"]
+        per_sweep = {k: (ms / cnt if cnt else None) for k, (ms, cnt) in r["profile"].items()}
+        sweeps = {k: per_sweep[k] for k in ("sweep_x", "sweep_y", "sweep_z")}
+        dom = max(sweeps, key=lambda k: r["profile"][k][0])
+        bytes_per_launch = 10 * s_bytes * cells
+        achieved = bytes_per_launch / (sweeps[dom] * 1e-3) / 1e9
+        return {
+            "gcell_updates_per_s": cells * args.steps / secs / 1e9,
+            "ms_per_step": secs / args.steps * 1e3,
+            "graph_ms_per_step": r["graph_seconds"] / args.steps * 1e3,
+            "algorithmic_GBps_step": 30 * s_bytes * cells * args.steps / secs / 1e9,
+            "kernel_ms": {k: round(v, 4) if v else v for k, v in per_sweep.items()},
+            "dominant": dom, "dominant_ms": sweeps[dom], "dominant_achieved_GBps": achieved,
+            "bytes_per_launch": bytes_per_launch, "status": r["status"],
+        }
+
+    f32 = measure(R.F32, 4)
+    print(f"[bench] fp32 {n}^3: {f32['gcell_updates_per_s']:.2f} Gcell-updates/s, "
+          f"{f32['ms_per_step']:.3f} ms/step, kernels {f32['kernel_ms']}", file=sys.stderr, flush=True)
+    f64 = None
+    if not args.no_f64:
+        f64 = measure(R.F64, 8)
+        print(f"[bench] fp64 {n}^3: {f64['gcell_updates_per_s']:.2f} Gcell-updates/s, "
+              f"{f64['ms_per_step']:.3f} ms/step, kernels {f64['kernel_ms']}", file=sys.stderr,
+              flush=True)
+
+    base = None
+    if args.cpu_steps > 0:
+        base = cpu_baseline(n, seed, args.cpu_steps)
+        print(f"[bench] cpu oracle: {base['value']:.4f} Gcell-updates/s on {base['cores']} "
+              "threads", file=sys.stderr, flush=True)
+
+    traffic = measured_traffic(f32["dominant"], f"{workload}_f32_{args.layout}")
+    out = {
+        "metric": "Gcell-updates/s and achieved HBM GB/s, 512^3 Euler step, FP32 vs FP64",
+        "value": round(f32["gcell_updates_per_s"], 4),
+        "unit": "Gcell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(f32["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded smooth periodic Fourier fields)",
+        "config": {"workload": workload, "cells": cells, "layout": args.layout,
+                   "tiling": args.tiling, "cfl": 0.9, "boundary": "periodic",
+                   "scheme": "split MUSCL-Hancock/minmod/HLLC, gamma 1.4"},
+        "achieved_GBps_algorithmic": round(f32["algorithmic_GBps_step"], 1),
+        "graph_ms_per_step": round(f32["graph_ms_per_step"], 4),
+        "kernel_ms": f32["kernel_ms"],
+        "roofline": {"bound": "hbm", "kernel": f32["dominant"],
+                     "achieved": round(f32["dominant_achieved_GBps"], 1), "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": round(f32["dominant_achieved_GBps"] / PEAK_HBM_GBS, 4),
+                     "traffic": traffic, "bytes_per_launch_algorithmic": f32["bytes_per_launch"],
+                     "mean_launch_ms": round(f32["dominant_ms"], 4)},
+        "cpu_baseline": base,
+    }
+    if f64 is not None:
+        out["f64"] = {"value": round(f64["gcell_updates_per_s"], 4), "unit": "Gcell-updates/s",
+                      "ms_per_step": round(f64["ms_per_step"], 4),
+                      "graph_ms_per_step": round(f64["graph_ms_per_step"], 4),
+                      "achieved_GBps_algorithmic": round(f64["algorithmic_GBps_step"], 1),
+                      "kernel_ms": f64["kernel_ms"],
+                      "dominant": f64["dominant"],
+                      "dominant_achieved_GBps": round(f64["dominant_achieved_GBps"], 1)}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

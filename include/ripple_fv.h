@@ -1,0 +1,268 @@
+/*
+ * ripple_fv.h -- padded-tile finite-volume Euler step for AMD Instinct MI355X
+ * (gfx950), C ABI.
+ *
+ * The library advances the three-dimensional compressible Euler equations
+ * (ideal gas, gamma = 1.4, conserved variables rho, rho u, rho v, rho w, E)
+ * by dimensionally split time steps on padded Cartesian grids.  One step
+ * follows the Ripple paper's Euler graph (section "Scaling Performance",
+ * listing "Simplified Euler solver graph creation"): per-cell wave speeds, a
+ * max reduction, the time step from that maximum, boundary padding, then an
+ * out-of-place update along x, then y, then z, with the two state buffers
+ * swapped between updates.  Each per-axis update is the MUSCL-Hancock scheme
+ * on conserved variables with the minmod slope and the HLLC Riemann solver
+ * with Davis wave speeds (Toro, "Riemann Solvers and Numerical Methods for
+ * Fluid Dynamics", sections 14.4 and 10.4); the paper leaves that update to
+ * the user.
+ *
+ * Storage follows the paper's padded tensors (section "Tensors": every block
+ * carries padding for stencil access) with a halo of two cells on every face,
+ * and its polymorphic data layout (section "Polymorphic Data Layout": the
+ * same cell type stored contiguously or strided), extended by a blocked
+ * layout.  With padded cell indices (i, j, k) -- interior cell (0, 0, 0) at
+ * (2, 2, 2) -- pitches Px, Py, Pz and q = (k Py + j) Px + i:
+ *
+ *   RIPPLE_FV_AOS    element (q, c) at  q * 5 + c            (contiguous)
+ *   RIPPLE_FV_SOA    element (q, c) at  c * Px Py Pz + q     (strided)
+ *   RIPPLE_FV_AOSOA  element (q, c) at  ((q / W) * 5 + c) * W + q % W,
+ *                    W = aosoa_w in {16, 32, 64}, Px a multiple of W
+ *
+ * Component order is (rho, m_x, m_y, m_z, E).  Elements are float (F32) or
+ * double (F64); the arithmetic of the update runs in that precision.
+ *
+ * Conventions shared by every entry point:
+ *  - Pointers named u, u_in, u_out, u_a, u_b, src, dst, ref, *_dev are device
+ *    pointers on the context's device, at least 256-byte aligned for state
+ *    buffers.  All large buffers belong to the caller; the library never
+ *    frees them.  A state buffer must hold at least grid.bytes bytes.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the legacy default
+ *    stream).  Work is enqueued asynchronously on it; the call returns once
+ *    enqueued.
+ *  - Return codes report host-side validation and HIP launch errors only.
+ *    On any error nothing has been enqueued.  A state the device finds
+ *    non-physical (rho <= 0, p <= 0 or non-finite) sets a sticky flag that
+ *    ripple_fv_check reports.
+ *  - A context is not thread-safe: use one context per host thread.
+ */
+#ifndef RIPPLE_FV_H
+#define RIPPLE_FV_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ripple_fv_status;
+
+enum ripple_fv_status_code {
+  RIPPLE_FV_OK = 0,
+  RIPPLE_FV_E_INVALID = 1,      /* bad argument: pointer, extent, enum, size */
+  RIPPLE_FV_E_UNSUPPORTED = 2,  /* valid but not supported (e.g. mixed layouts in a batch) */
+  RIPPLE_FV_E_DEVICE = 3,       /* a HIP call failed; see ripple_fv_last_error */
+  RIPPLE_FV_E_NONPHYSICAL = 4,  /* the device met rho <= 0, p <= 0 or a non-finite value */
+  RIPPLE_FV_E_NOMEM = 5         /* a workspace allocation failed */
+};
+
+enum ripple_fv_layout { RIPPLE_FV_AOS = 0, RIPPLE_FV_SOA = 1, RIPPLE_FV_AOSOA = 2 };
+enum ripple_fv_dtype { RIPPLE_FV_F32 = 0, RIPPLE_FV_F64 = 1 };
+enum ripple_fv_bc { RIPPLE_FV_TRANSMISSIVE = 0, RIPPLE_FV_PERIODIC = 1 };
+enum ripple_fv_variables { RIPPLE_FV_PRIMITIVE = 0, RIPPLE_FV_CONSERVED = 1 };
+
+/* ripple_fv_run_batch flags (bitwise or). */
+enum ripple_fv_run_flags {
+  RIPPLE_FV_RUN_EAGER = 0,     /* one persistent launch per kernel per step */
+  RIPPLE_FV_RUN_GRAPH = 1,     /* replay a captured hipGraph of the step loop */
+  RIPPLE_FV_RUN_PER_GRID = 2,  /* one launch per grid per kernel (baseline) */
+  RIPPLE_FV_RUN_PROFILE = 4    /* eager, with hipEvents around every launch */
+};
+
+/* Kernel kinds reported by ripple_fv_profile. */
+enum ripple_fv_kernel_kind {
+  RIPPLE_FV_K_WAVESPEED = 0, RIPPLE_FV_K_DT = 1, RIPPLE_FV_K_SWEEP_X = 2,
+  RIPPLE_FV_K_SWEEP_Y = 3, RIPPLE_FV_K_SWEEP_Z = 4, RIPPLE_FV_K_HALO = 5,
+  RIPPLE_FV_NKERNELS = 6
+};
+
+#define RIPPLE_FV_HALO 2
+#define RIPPLE_FV_NVAR 5
+
+/* Grid descriptor.  Fill the inputs, then call ripple_fv_grid_init.
+ *
+ *  n        interior extents (x, y, z), each >= 2
+ *  bc       boundary condition per axis, applied on both faces that are
+ *           physical boundaries (transmissive = constant extrapolation of the
+ *           edge cell into the padding; periodic = wrap)
+ *  dx       cell widths (> 0); a unit cube has dx[d] = 1 / n[d]
+ *  layout, dtype, aosoa_w   storage (aosoa_w in {16, 32, 64} for AOSOA, else 0)
+ *  group    grids with the same group share one time step (the sub-blocks of
+ *           a partitioned domain); -1 = the grid's own.  A group is named by
+ *           the batch index of its first member, which must name itself.
+ *  nbr      sub-block links per face (-x, +x, -y, +y, -z, +z): batch index of
+ *           the neighbouring sub-block whose interior fills this face's
+ *           padding, or -1 when the face is a physical boundary
+ *  x_block, yz_block, yz_segment, persist   kernel tiling chosen by
+ *           ripple_fv_batch_tune (0 = defaults); they never change results
+ *  pitch, bytes   OUT: padded extents (Px, Py, Pz) and bytes of one buffer */
+typedef struct ripple_fv_grid {
+  int32_t n[3];
+  int32_t bc[3];
+  double dx[3];
+  int32_t layout;
+  int32_t dtype;
+  int32_t aosoa_w;
+  int32_t group;
+  int32_t nbr[6];
+  int32_t x_block;
+  int32_t yz_block;
+  int32_t yz_segment;
+  int32_t persist;
+  int64_t pitch[3];
+  int64_t bytes;
+} ripple_fv_grid;
+
+typedef struct ripple_fv_ctx ripple_fv_ctx;
+
+/* Validate a descriptor and fill pitch[] and bytes.  Px = n[0] + 4 rounded
+ * up to a multiple of aosoa_w for AOSOA; Py = n[1] + 4; Pz = n[2] + 4
+ * (section "Tensors": padding is part of the tensor's storage).
+ * E_INVALID on extents < 2, dx <= 0, unknown enums, bad aosoa_w, bad tiling
+ * knobs, or a buffer size above 2^46 bytes. */
+ripple_fv_status ripple_fv_grid_init(ripple_fv_grid* g);
+
+/* Create a context on HIP device `device`.  The context owns only small
+ * preallocated workspaces (flags, reduction partials, per-batch plans and
+ * captured graphs).  E_INVALID for a bad device or NULL ctx, E_DEVICE or
+ * E_NOMEM on failure. */
+ripple_fv_status ripple_fv_create(ripple_fv_ctx** ctx, int32_t device);
+void ripple_fv_destroy(ripple_fv_ctx* ctx);
+
+/* Load an initial state.  src: FP64 planar device array [5][n2][n1][n0],
+ * holding primitive (rho, u, v, w, p) or conserved variables per
+ * `variables`.  Primitive input is converted with E = p / (gamma - 1) +
+ * rho |u|^2 / 2 in FP64, then rounded to the grid's precision.  Writes the
+ * interior of u; padding is left untouched. */
+ripple_fv_status ripple_fv_import(ripple_fv_ctx* ctx, const ripple_fv_grid* g,
+                                  const double* src, int32_t variables, void* u,
+                                  void* stream);
+
+/* Copy the interior of u out as FP64 conserved variables, planar
+ * [5][n2][n1][n0] (dst, device). */
+ripple_fv_status ripple_fv_export(ripple_fv_ctx* ctx, const ripple_fv_grid* g, const void* u,
+                                  double* dst, void* stream);
+
+/* Convert the interior of src (grid gs) into dst (grid gd): layout and/or
+ * precision change (the paper's polymorphic layout, section "Polymorphic Data
+ * Layout").  gs and gd must have equal n.  FP64 -> FP32 rounds to nearest. */
+ripple_fv_status ripple_fv_convert(ripple_fv_ctx* ctx, const ripple_fv_grid* gs, const void* src,
+                                   const ripple_fv_grid* gd, void* dst, void* stream);
+
+/* Maximum signal speeds S_d = max over interior cells of |u_d| + c,
+ * c = sqrt(gamma p / rho), d = x, y, z (the paper's set_wavespeeds node
+ * followed by its max reduction, section "Graphs", paragraph "Reduction").
+ * s_dev: 3 doubles (device).  The maximum is exact, so the result does not
+ * depend on the reduction order. */
+ripple_fv_status ripple_fv_max_wavespeed(ripple_fv_ctx* ctx, const ripple_fv_grid* g,
+                                         const void* u, double* s_dev, void* stream);
+
+/* One sweep along `axis` (0, 1, 2) with time step dt > 0: u_out = the
+ * MUSCL-Hancock/HLLC update of u_in along that axis (the paper's
+ * update_state_x / update_state_y nodes with concurrent padded access:
+ * read u_in and its padding, write u_out).  Physical faces take the
+ * boundary condition; faces with a neighbour read u_in's padding, which
+ * ripple_fv_halo_exchange fills.  u_in is not modified. */
+ripple_fv_status ripple_fv_sweep(ripple_fv_ctx* ctx, const ripple_fv_grid* g, int32_t axis,
+                                 const void* u_in, void* u_out, double dt, void* stream);
+
+/* One full step: wave speeds -> dt = cfl * min_d dx_d / S_d (or the fixed
+ * dt when dt > 0) -> sweep x (u_in -> u_out) -> sweep y (u_out -> u_in) ->
+ * sweep z (u_in -> u_out).  The new state is in u_out; u_in is clobbered
+ * (the paper's swap_in_out is left to the caller).  cfl in (0, 1].
+ * dt_dev: optional device double receiving the dt used. */
+ripple_fv_status ripple_fv_step(ripple_fv_ctx* ctx, const ripple_fv_grid* g, void* u_in,
+                                void* u_out, double cfl, double dt, double* dt_dev,
+                                void* stream);
+
+/* Advance n independent grids (or sub-blocks of partitioned domains) by
+ * nsteps steps.  Every grid uses its group's dt from the CFL condition.
+ * u_a[i], u_b[i]: the two buffers of grid i; the initial state is in u_a.
+ * Each step runs x (a -> b), y (b -> a), z (a -> b) and then swaps the
+ * roles, so after nsteps the result is in u_b when nsteps is odd and in u_a
+ * when it is even.  Before each sweep along d, faces with a neighbour get
+ * their padding copied from the neighbour's interior (the paper's
+ * concurrent padded access, section "Tensor Data Dependencies").
+ * All grids must share layout and dtype (else E_UNSUPPORTED).
+ * flags: ripple_fv_run_flags.  The first call for a given set of grid
+ * descriptors builds and caches a plan (workspaces, tile lists, graphs);
+ * later calls with the same descriptors allocate nothing. */
+ripple_fv_status ripple_fv_run_batch(ripple_fv_ctx* ctx, int32_t n, const ripple_fv_grid* grids,
+                                     void* const* u_a, void* const* u_b, int32_t nsteps,
+                                     double cfl, int32_t flags, void* stream);
+
+/* Time reached (t_host[i], since the start of the last ripple_fv_run_batch
+ * call on this grid set) and the last dt per grid (dt_host, may be NULL).
+ * Synchronises the device. */
+ripple_fv_status ripple_fv_batch_time(ripple_fv_ctx* ctx, int32_t n, const ripple_fv_grid* grids,
+                                      double* t_host, double* dt_host);
+
+/* Choose layout and tiling for a batch by timing candidates on the device
+ * (the paper motivates this: trying every layout by hand is cumbersome,
+ * section "Introduction").  `in`: the batch's descriptors (layout fields
+ * ignored); `chosen`: OUT, n descriptors with layout, aosoa_w, tiling knobs,
+ * pitch and bytes filled.  Allocates temporary buffers; synchronises the
+ * device; results are cached in the context per (dtype, extents) set. */
+ripple_fv_status ripple_fv_batch_tune(ripple_fv_ctx* ctx, int32_t n, const ripple_fv_grid* in,
+                                      ripple_fv_grid* chosen, void* stream);
+
+/* Split a grid into parts[0] x parts[1] x parts[2] sub-blocks on one device
+ * (the paper's sub-partitions, section "Tensors").  sub: OUT, the product
+ * of parts descriptors, x fastest, each with its own extents (extents split
+ * as evenly as possible), dx, nbr links (batch indices offset by
+ * first_index) and group = first_index.  The whole grid's periodic axes are
+ * linked around. */
+ripple_fv_status ripple_fv_partition(const ripple_fv_grid* whole, const int32_t parts[3],
+                                     int32_t first_index, ripple_fv_grid* sub);
+
+/* Copy the two interior layers next to each linked face along `axis` from
+ * the neighbour into the face's padding, for every grid of the batch
+ * (the paper's padding-copy nodes, section "Tensor Data Dependencies",
+ * "Concurrent access with padding").  u[i]: the buffer of grid i. */
+ripple_fv_status ripple_fv_halo_exchange(ripple_fv_ctx* ctx, int32_t n,
+                                         const ripple_fv_grid* grids, void* const* u,
+                                         int32_t axis, void* stream);
+
+/* Sums over interior cells of each conserved variable, accumulated in FP64
+ * in a fixed order (deterministic): sums_dev, 5 doubles (device). */
+ripple_fv_status ripple_fv_conserved_sums(ripple_fv_ctx* ctx, const ripple_fv_grid* g,
+                                          const void* u, double* sums_dev, void* stream);
+
+/* Error norms of u against ref (FP64 conserved, planar [5][n2][n1][n0],
+ * device), accumulated in FP64: out_dev (device, 20 doubles) receives per
+ * variable c the four values sum|u - ref|, sum|ref|, max|u - ref|, max|ref|
+ * at out_dev[4 c + 0..3]. */
+ripple_fv_status ripple_fv_error_norms(ripple_fv_ctx* ctx, const ripple_fv_grid* g,
+                                       const void* u, const double* ref_dev, double* out_dev,
+                                       void* stream);
+
+/* Wait for the device, then report and clear the sticky non-physical flag:
+ * E_NONPHYSICAL if any kernel since the last check met rho <= 0, p <= 0 or
+ * a non-finite value (wave-speed kernel and the last sweep of every step),
+ * else OK. */
+ripple_fv_status ripple_fv_check(ripple_fv_ctx* ctx);
+
+/* Kernel times recorded by RIPPLE_FV_RUN_PROFILE runs since the last call:
+ * ms[k] total milliseconds and launches[k] launch counts per
+ * ripple_fv_kernel_kind (arrays of RIPPLE_FV_NKERNELS).  Clears them. */
+ripple_fv_status ripple_fv_profile(ripple_fv_ctx* ctx, double* ms, int64_t* launches);
+
+/* Static description of a status code. */
+const char* ripple_fv_status_string(ripple_fv_status s);
+
+/* Text of the last error on this context ("" if none). */
+const char* ripple_fv_last_error(ripple_fv_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RIPPLE_FV_H */

@@ -1,0 +1,1055 @@
+// C ABI of libripple_fv: argument validation, contexts, cached per-batch plans
+// (device workspaces, tile lists, halo task lists, captured graphs), the step
+// loop, diagnostics and the layout / tiling autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "fv_internal.hpp"
+#include "ripple_fv.h"
+
+using namespace rfv;
+
+namespace {
+
+constexpr int64_t MAX_BYTES = int64_t(1) << 46;
+constexpr int MAX_PLANS = 16;
+
+struct Plan {
+  int n = 0;
+  int dtype = 0, lay = 0;
+  Tiling tl{};
+  std::vector<ripple_fv_grid> grids;
+  std::vector<int64_t> tiles[4];        // prefix: x, y, z, wave-speed tiles
+  std::vector<HaloTask> halo[3];
+  int64_t halo_area[3] = {0, 0, 0};
+  // device workspace (one allocation) and its views
+  void* dmem = nullptr;
+  DevGrid* d_grids = nullptr;
+  int64_t* d_tiles[4] = {nullptr, nullptr, nullptr, nullptr};
+  HaloTask* d_halo[3] = {nullptr, nullptr, nullptr};
+  double* d_lam = nullptr;
+  double* d_t = nullptr;
+  double* d_dt = nullptr;
+  unsigned long long* d_s = nullptr;
+  // descriptor staging for buffer-pointer updates
+  std::vector<DevGrid> h_grids;
+  DevGrid* h_pinned = nullptr;
+  hipEvent_t upload_done = nullptr;
+  bool upload_pending = false;
+  bool uploaded = false;
+  // captured step graphs (one step, two steps) and the cfl they were captured with
+  hipGraphExec_t g1 = nullptr, g2 = nullptr;
+  double graph_cfl = -1.0;
+
+  ~Plan() {
+    if (g1) hipGraphExecDestroy(g1);
+    if (g2) hipGraphExecDestroy(g2);
+    if (upload_done) {
+      hipEventSynchronize(upload_done);
+      hipEventDestroy(upload_done);
+    }
+    if (h_pinned) hipHostFree(h_pinned);
+    if (dmem) hipFree(dmem);
+  }
+  Work work(unsigned int* flag) const {
+    Work w;
+    w.grids = d_grids;
+    w.ngrids = n;
+    w.pad_ = 0;
+    w.lam = d_lam;
+    w.t = d_t;
+    w.dt = d_dt;
+    w.s_acc = d_s;
+    w.flag = flag;
+    return w;
+  }
+};
+
+}  // namespace
+
+struct ripple_fv_ctx {
+  int device = 0;
+  int cu_count = 256;
+  std::string err;
+  unsigned int* flag = nullptr;     // device
+  double* partials = nullptr;       // device, DIAG_MAX_BLOCKS * 20
+  hipStream_t cap_stream = nullptr; // private stream used only for graph capture
+  std::map<std::string, std::unique_ptr<Plan>> plans;
+  std::deque<std::string> plan_order;
+  std::vector<hipEvent_t> events;   // profiling event pool
+  double prof_ms[RIPPLE_FV_NKERNELS] = {0};
+  int64_t prof_n[RIPPLE_FV_NKERNELS] = {0};
+  std::map<std::string, std::vector<ripple_fv_grid>> tune_cache;
+};
+
+namespace {
+
+ripple_fv_status fail(ripple_fv_ctx* ctx, ripple_fv_status st, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  return st;
+}
+
+#define HIP_OR_FAIL(ctx, call)                                                            \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return fail((ctx), RIPPLE_FV_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+bool valid_block(int v, std::initializer_list<int> allowed) {
+  return std::find(allowed.begin(), allowed.end(), v) != allowed.end();
+}
+
+// Validate a descriptor and compute its pitches and size (ripple_fv_grid_init).
+ripple_fv_status grid_check(const ripple_fv_grid* g, int64_t pitch[3], int64_t* bytes,
+                            std::string* why) {
+  for (int d = 0; d < 3; ++d) {
+    if (g->n[d] < 2) { *why = "extent < 2"; return RIPPLE_FV_E_INVALID; }
+    if (!(g->dx[d] > 0.0) || !std::isfinite(g->dx[d])) { *why = "dx <= 0"; return RIPPLE_FV_E_INVALID; }
+    if (g->bc[d] != RIPPLE_FV_TRANSMISSIVE && g->bc[d] != RIPPLE_FV_PERIODIC) {
+      *why = "unknown boundary condition";
+      return RIPPLE_FV_E_INVALID;
+    }
+  }
+  if (g->dtype != RIPPLE_FV_F32 && g->dtype != RIPPLE_FV_F64) { *why = "unknown dtype"; return RIPPLE_FV_E_INVALID; }
+  if (g->layout == RIPPLE_FV_AOSOA) {
+    if (!valid_block(g->aosoa_w, {16, 32, 64})) { *why = "aosoa_w must be 16, 32 or 64"; return RIPPLE_FV_E_INVALID; }
+  } else if (g->layout == RIPPLE_FV_AOS || g->layout == RIPPLE_FV_SOA) {
+    if (g->aosoa_w != 0) { *why = "aosoa_w must be 0 unless layout is AOSOA"; return RIPPLE_FV_E_INVALID; }
+  } else {
+    *why = "unknown layout";
+    return RIPPLE_FV_E_INVALID;
+  }
+  if (!valid_block(g->x_block, {0, 128, 256}) || !valid_block(g->yz_block, {0, 64, 128, 256}) ||
+      g->yz_segment < 0 || (g->yz_segment > 0 && g->yz_segment < 4) || g->yz_segment > 4096 ||
+      g->persist < 0 || g->persist > 64) {
+    *why = "bad tiling knobs";
+    return RIPPLE_FV_E_INVALID;
+  }
+  int64_t px = g->n[0] + 4;
+  if (g->layout == RIPPLE_FV_AOSOA) px = (px + g->aosoa_w - 1) / g->aosoa_w * g->aosoa_w;
+  const int64_t py = g->n[1] + 4, pz = g->n[2] + 4;
+  const int64_t cells = px * py * pz;
+  const int64_t elem = g->dtype == RIPPLE_FV_F32 ? 4 : 8;
+  // 32-bit tile-local index spaces in the kernels
+  if ((int64_t)(g->n[0] + 4) * g->n[1] * g->n[2] >= (int64_t(1) << 31) || cells >= (int64_t(1) << 40)) {
+    *why = "grid too large";
+    return RIPPLE_FV_E_INVALID;
+  }
+  const int64_t b = cells * 5 * elem;
+  if (b > MAX_BYTES) { *why = "grid too large"; return RIPPLE_FV_E_INVALID; }
+  pitch[0] = px;
+  pitch[1] = py;
+  pitch[2] = pz;
+  *bytes = b;
+  return RIPPLE_FV_OK;
+}
+
+Tiling tiling_of(const ripple_fv_grid& g) {
+  Tiling t;
+  t.x_block = g.x_block ? g.x_block : 256;
+  t.yz_block = g.yz_block ? g.yz_block : 256;
+  t.yz_segment = g.yz_segment ? g.yz_segment : 64;
+  t.persist = g.persist;
+  return t;
+}
+
+// A descriptor must have been through ripple_fv_grid_init (pitch, bytes filled).
+ripple_fv_status grid_ok(ripple_fv_ctx* ctx, const ripple_fv_grid* g) {
+  if (!g) return fail(ctx, RIPPLE_FV_E_INVALID, "NULL grid");
+  int64_t pitch[3], bytes;
+  std::string why;
+  ripple_fv_status st = grid_check(g, pitch, &bytes, &why);
+  if (st != RIPPLE_FV_OK) return fail(ctx, st, why);
+  if (pitch[0] != g->pitch[0] || pitch[1] != g->pitch[1] || pitch[2] != g->pitch[2] ||
+      bytes != g->bytes)
+    return fail(ctx, RIPPLE_FV_E_INVALID, "grid not initialised (call ripple_fv_grid_init)");
+  return RIPPLE_FV_OK;
+}
+
+// Device pointer check: non-NULL, 256-byte aligned (state buffers), and inside a
+// device allocation with at least `bytes` bytes from it.
+ripple_fv_status ptr_ok(ripple_fv_ctx* ctx, const void* p, int64_t bytes, int64_t align,
+                        const char* what) {
+  if (!p) return fail(ctx, RIPPLE_FV_E_INVALID, std::string("NULL ") + what);
+  if (reinterpret_cast<uintptr_t>(p) % align != 0)
+    return fail(ctx, RIPPLE_FV_E_INVALID, std::string(what) + " misaligned");
+  hipDeviceptr_t base = nullptr;
+  size_t size = 0;
+  if (hipMemGetAddressRange(&base, &size, const_cast<void*>(p)) != hipSuccess || !base) {
+    (void)hipGetLastError();
+    return fail(ctx, RIPPLE_FV_E_INVALID, std::string(what) + " is not device memory");
+  }
+  const char* b = static_cast<const char*>(base);
+  const char* q = static_cast<const char*>(p);
+  if (q < b || q + bytes > b + size)
+    return fail(ctx, RIPPLE_FV_E_INVALID, std::string(what) + " is smaller than required");
+  return RIPPLE_FV_OK;
+}
+
+Desc desc_of(const ripple_fv_grid& g, const void* buf) {
+  Desc d;
+  d.buf = const_cast<void*>(buf);
+  for (int i = 0; i < 3; ++i) d.n[i] = g.n[i];
+  d.lay = lay_of(g);
+  d.dtype = g.dtype;
+  d.pad_ = 0;
+  d.px = g.pitch[0];
+  d.pxy = g.pitch[0] * g.pitch[1];
+  d.ptot = d.pxy * g.pitch[2];
+  return d;
+}
+
+int group_of(const ripple_fv_grid& g, int index) { return g.group < 0 ? index : g.group; }
+
+// Plan key: the descriptors' bytes (buffer pointers are not part of it).
+std::string plan_key(int n, const ripple_fv_grid* grids) {
+  return std::string(reinterpret_cast<const char*>(grids), sizeof(ripple_fv_grid) * (size_t)n);
+}
+
+ripple_fv_status validate_batch(ripple_fv_ctx* ctx, int n, const ripple_fv_grid* grids) {
+  if (n < 1 || !grids) return fail(ctx, RIPPLE_FV_E_INVALID, "empty batch");
+  for (int g = 0; g < n; ++g) {
+    ripple_fv_status st = grid_ok(ctx, &grids[g]);
+    if (st) return st;
+  }
+  const ripple_fv_grid& g0 = grids[0];
+  for (int g = 1; g < n; ++g) {
+    const ripple_fv_grid& G = grids[g];
+    if (G.dtype != g0.dtype || G.layout != g0.layout || G.aosoa_w != g0.aosoa_w)
+      return fail(ctx, RIPPLE_FV_E_UNSUPPORTED, "grids of a batch must share layout and dtype");
+    if (G.x_block != g0.x_block || G.yz_block != g0.yz_block || G.yz_segment != g0.yz_segment ||
+        G.persist != g0.persist)
+      return fail(ctx, RIPPLE_FV_E_UNSUPPORTED, "grids of a batch must share tiling knobs");
+  }
+  for (int g = 0; g < n; ++g) {
+    const ripple_fv_grid& G = grids[g];
+    const int grp = group_of(G, g);
+    if (grp < 0 || grp >= n) return fail(ctx, RIPPLE_FV_E_INVALID, "group index out of range");
+    if (group_of(grids[grp], grp) != grp)
+      return fail(ctx, RIPPLE_FV_E_INVALID, "group leader must belong to its own group");
+    for (int d = 0; d < 3; ++d)
+      if (grids[grp].dx[d] != G.dx[d])
+        return fail(ctx, RIPPLE_FV_E_INVALID, "grids of a group must share dx");
+    for (int f = 0; f < 6; ++f) {
+      const int h = G.nbr[f];
+      if (h < 0) {
+        if (h != -1) return fail(ctx, RIPPLE_FV_E_INVALID, "bad neighbour index");
+        continue;
+      }
+      if (h >= n) return fail(ctx, RIPPLE_FV_E_INVALID, "neighbour index out of range");
+      const int axis = f / 2;
+      const ripple_fv_grid& H = grids[h];
+      for (int d = 0; d < 3; ++d)
+        if (d != axis && H.n[d] != G.n[d])
+          return fail(ctx, RIPPLE_FV_E_INVALID, "linked sub-blocks must match across the face");
+      if (H.nbr[f ^ 1] != g)
+        return fail(ctx, RIPPLE_FV_E_INVALID, "sub-block links must be reciprocal");
+      if (H.n[axis] < 2) return fail(ctx, RIPPLE_FV_E_INVALID, "neighbour too thin");
+    }
+  }
+  return RIPPLE_FV_OK;
+}
+
+ripple_fv_status build_plan(ripple_fv_ctx* ctx, int n, const ripple_fv_grid* grids, Plan** out) {
+  const std::string key = plan_key(n, grids);
+  auto it = ctx->plans.find(key);
+  if (it != ctx->plans.end()) {
+    *out = it->second.get();
+    return RIPPLE_FV_OK;
+  }
+  std::unique_ptr<Plan> P(new Plan());
+  P->n = n;
+  P->dtype = grids[0].dtype;
+  P->lay = lay_of(grids[0]);
+  P->tl = tiling_of(grids[0]);
+  P->grids.assign(grids, grids + n);
+  for (int k = 0; k < 4; ++k) P->tiles[k].assign(n + 1, 0);
+  for (int g = 0; g < n; ++g) {
+    P->tiles[0][g + 1] = P->tiles[0][g] + tiles_x(grids[g], P->tl.x_block);
+    P->tiles[1][g + 1] = P->tiles[1][g] + tiles_yz(grids[g], 1, P->tl.yz_block, P->tl.yz_segment);
+    P->tiles[2][g + 1] = P->tiles[2][g] + tiles_yz(grids[g], 2, P->tl.yz_block, P->tl.yz_segment);
+    P->tiles[3][g + 1] = P->tiles[3][g] + tiles_ws(grids[g]);
+  }
+  for (int axis = 0; axis < 3; ++axis) {
+    for (int g = 0; g < n; ++g) {
+      const ripple_fv_grid& G = grids[g];
+      for (int side = 0; side < 2; ++side) {
+        const int h = G.nbr[2 * axis + side];
+        if (h < 0) continue;
+        HaloTask t;
+        t.dst = g;
+        t.src = h;
+        t.side = side;
+        t.pad_ = 0;
+        P->halo[axis].push_back(t);
+        const int64_t area = (int64_t)G.n[axis == 0 ? 1 : 0] * G.n[axis == 2 ? 1 : 2];
+        P->halo_area[axis] = std::max(P->halo_area[axis], area);
+      }
+    }
+  }
+  // host descriptors (buffer pointers filled per call)
+  P->h_grids.resize(n);
+  for (int g = 0; g < n; ++g) {
+    const ripple_fv_grid& G = grids[g];
+    DevGrid& D = P->h_grids[g];
+    std::memset(&D, 0, sizeof(D));
+    for (int d = 0; d < 3; ++d) {
+      D.n[d] = G.n[d];
+      D.dx[d] = G.dx[d];
+      for (int side = 0; side < 2; ++side) {
+        const int f = 2 * d + side;
+        D.mode[f] = G.nbr[f] >= 0 ? FACE_HALO
+                                  : (G.bc[d] == RIPPLE_FV_PERIODIC ? FACE_PERIODIC : FACE_TRANSMISSIVE);
+      }
+    }
+    D.px = G.pitch[0];
+    D.pxy = G.pitch[0] * G.pitch[1];
+    D.ptot = D.pxy * G.pitch[2];
+    D.group = group_of(G, g);
+  }
+  // device workspace
+  auto align = [](size_t v) { return (v + 255) & ~size_t(255); };
+  size_t off = 0;
+  const size_t o_grids = off; off = align(off + sizeof(DevGrid) * n);
+  size_t o_tiles[4];
+  for (int k = 0; k < 4; ++k) { o_tiles[k] = off; off = align(off + sizeof(int64_t) * (n + 1)); }
+  size_t o_halo[3];
+  for (int k = 0; k < 3; ++k) { o_halo[k] = off; off = align(off + sizeof(HaloTask) * (P->halo[k].size() + 1)); }
+  const size_t o_lam = off; off = align(off + sizeof(double) * 3 * n);
+  const size_t o_t = off; off = align(off + sizeof(double) * n);
+  const size_t o_dt = off; off = align(off + sizeof(double) * n);
+  const size_t o_s = off; off = align(off + sizeof(unsigned long long) * 3 * n);
+  if (hipMalloc(&P->dmem, off) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(ctx, RIPPLE_FV_E_NOMEM, "plan workspace allocation failed");
+  }
+  char* base = static_cast<char*>(P->dmem);
+  P->d_grids = reinterpret_cast<DevGrid*>(base + o_grids);
+  for (int k = 0; k < 4; ++k) P->d_tiles[k] = reinterpret_cast<int64_t*>(base + o_tiles[k]);
+  for (int k = 0; k < 3; ++k) P->d_halo[k] = reinterpret_cast<HaloTask*>(base + o_halo[k]);
+  P->d_lam = reinterpret_cast<double*>(base + o_lam);
+  P->d_t = reinterpret_cast<double*>(base + o_t);
+  P->d_dt = reinterpret_cast<double*>(base + o_dt);
+  P->d_s = reinterpret_cast<unsigned long long*>(base + o_s);
+  for (int k = 0; k < 4; ++k)
+    HIP_OR_FAIL(ctx, hipMemcpy(P->d_tiles[k], P->tiles[k].data(), sizeof(int64_t) * (n + 1),
+                               hipMemcpyHostToDevice));
+  for (int k = 0; k < 3; ++k)
+    if (!P->halo[k].empty())
+      HIP_OR_FAIL(ctx, hipMemcpy(P->d_halo[k], P->halo[k].data(),
+                                 sizeof(HaloTask) * P->halo[k].size(), hipMemcpyHostToDevice));
+  HIP_OR_FAIL(ctx, hipMemset(P->d_lam, 0, sizeof(double) * 3 * n));
+  HIP_OR_FAIL(ctx, hipMemset(P->d_t, 0, sizeof(double) * n));
+  HIP_OR_FAIL(ctx, hipMemset(P->d_dt, 0, sizeof(double) * n));
+  HIP_OR_FAIL(ctx, hipMemset(P->d_s, 0, sizeof(unsigned long long) * 3 * n));
+  HIP_OR_FAIL(ctx, hipHostMalloc(reinterpret_cast<void**>(&P->h_pinned), sizeof(DevGrid) * n,
+                                 hipHostMallocDefault));
+  HIP_OR_FAIL(ctx, hipEventCreateWithFlags(&P->upload_done, hipEventDisableTiming));
+  if ((int)ctx->plans.size() >= MAX_PLANS) {
+    HIP_OR_FAIL(ctx, hipDeviceSynchronize());
+    ctx->plans.erase(ctx->plan_order.front());
+    ctx->plan_order.pop_front();
+  }
+  *out = P.get();
+  ctx->plan_order.push_back(key);
+  ctx->plans[key] = std::move(P);
+  return RIPPLE_FV_OK;
+}
+
+// Put the current buffer pointers into the plan's device descriptors
+// (stream-ordered; skipped when unchanged since the last upload).
+ripple_fv_status upload_buffers(ripple_fv_ctx* ctx, Plan* P, void* const* a, void* const* b,
+                                hipStream_t s) {
+  bool changed = !P->uploaded;
+  for (int g = 0; g < P->n; ++g) {
+    void* na = a[g];
+    void* nb = b ? b[g] : nullptr;
+    if (P->h_grids[g].buf[0] != na || P->h_grids[g].buf[1] != nb) changed = true;
+    P->h_grids[g].buf[0] = na;
+    P->h_grids[g].buf[1] = nb;
+  }
+  if (!changed) return RIPPLE_FV_OK;
+  if (P->upload_pending) HIP_OR_FAIL(ctx, hipEventSynchronize(P->upload_done));
+  std::memcpy(P->h_pinned, P->h_grids.data(), sizeof(DevGrid) * P->n);
+  HIP_OR_FAIL(ctx, hipMemcpyAsync(P->d_grids, P->h_pinned, sizeof(DevGrid) * P->n,
+                                  hipMemcpyHostToDevice, s));
+  HIP_OR_FAIL(ctx, hipEventRecord(P->upload_done, s));
+  P->upload_pending = true;
+  P->uploaded = true;
+  return RIPPLE_FV_OK;
+}
+
+int blocks_for(const ripple_fv_ctx* ctx, const Tiling& tl, int64_t tiles) {
+  int64_t b = tiles;
+  if (tl.persist > 0) b = std::min<int64_t>(tiles, (int64_t)tl.persist * ctx->cu_count);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(b, 0x7fffffff));
+}
+
+// Launches of one kernel kind, optionally bracketed by profiling events.
+struct Launcher {
+  ripple_fv_ctx* ctx;
+  hipStream_t s;
+  bool profile;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> marks;
+  size_t next_event = 0;
+  ripple_fv_status begin(int kind, hipEvent_t* e1) {
+    if (!profile) return RIPPLE_FV_OK;
+    if (next_event + 2 > ctx->events.size()) {
+      for (int i = 0; i < 64; ++i) {
+        hipEvent_t e;
+        HIP_OR_FAIL(ctx, hipEventCreate(&e));
+        ctx->events.push_back(e);
+      }
+    }
+    hipEvent_t a = ctx->events[next_event], b = ctx->events[next_event + 1];
+    next_event += 2;
+    HIP_OR_FAIL(ctx, hipEventRecord(a, s));
+    marks.push_back({kind, {a, b}});
+    *e1 = b;
+    return RIPPLE_FV_OK;
+  }
+  ripple_fv_status end(hipEvent_t e1) {
+    if (!profile) return RIPPLE_FV_OK;
+    HIP_OR_FAIL(ctx, hipEventRecord(e1, s));
+    return RIPPLE_FV_OK;
+  }
+  ripple_fv_status collect() {
+    if (!profile || marks.empty()) return RIPPLE_FV_OK;
+    HIP_OR_FAIL(ctx, hipEventSynchronize(marks.back().second.second));
+    for (auto& m : marks) {
+      float ms = 0.f;
+      HIP_OR_FAIL(ctx, hipEventElapsedTime(&ms, m.second.first, m.second.second));
+      ctx->prof_ms[m.first] += ms;
+      ctx->prof_n[m.first] += 1;
+    }
+    marks.clear();
+    next_event = 0;
+    return RIPPLE_FV_OK;
+  }
+};
+
+#define LAUNCH_OR_FAIL(ctx, call) HIP_OR_FAIL(ctx, call)
+
+// Enqueue one sweep along `axis` for every grid (persistent launch over the
+// batch's tile list, or one launch per grid).
+ripple_fv_status enqueue_sweep(ripple_fv_ctx* ctx, Plan* P, Launcher& L, int axis, int in, int out,
+                               int fuse_s, bool per_grid) {
+  SweepParams sp;
+  sp.w = P->work(ctx->flag);
+  sp.in = in;
+  sp.out = out;
+  sp.seg = P->tl.yz_segment;
+  sp.fuse_s = fuse_s;
+  sp.tiles.tile_start = P->d_tiles[axis];
+  hipEvent_t e1 = nullptr;
+  ripple_fv_status st = L.begin(RIPPLE_FV_K_SWEEP_X + axis, &e1);
+  if (st) return st;
+  const std::vector<int64_t>& pre = P->tiles[axis];
+  if (per_grid) {
+    for (int g = 0; g < P->n; ++g) {
+      sp.tiles.first = pre[g];
+      sp.tiles.count = pre[g + 1] - pre[g];
+      LAUNCH_OR_FAIL(ctx, launch_sweep(P->dtype, P->lay, axis, P->tl, sp,
+                                       blocks_for(ctx, P->tl, sp.tiles.count), L.s));
+    }
+  } else {
+    sp.tiles.first = 0;
+    sp.tiles.count = pre[P->n];
+    LAUNCH_OR_FAIL(ctx, launch_sweep(P->dtype, P->lay, axis, P->tl, sp,
+                                     blocks_for(ctx, P->tl, sp.tiles.count), L.s));
+  }
+  return L.end(e1);
+}
+
+ripple_fv_status enqueue_halo(ripple_fv_ctx* ctx, Plan* P, Launcher& L, int axis, int buf) {
+  if (P->halo[axis].empty()) return RIPPLE_FV_OK;
+  hipEvent_t e1 = nullptr;
+  ripple_fv_status st = L.begin(RIPPLE_FV_K_HALO, &e1);
+  if (st) return st;
+  LAUNCH_OR_FAIL(ctx, launch_halo(P->dtype, P->lay, P->work(ctx->flag), buf, axis, P->d_halo[axis],
+                                  (int)P->halo[axis].size(), P->halo_area[axis], L.s));
+  return L.end(e1);
+}
+
+ripple_fv_status enqueue_wavespeed(ripple_fv_ctx* ctx, Plan* P, Launcher& L, int buf,
+                                   unsigned long long* s_out, bool per_grid) {
+  hipEvent_t e1 = nullptr;
+  ripple_fv_status st = L.begin(RIPPLE_FV_K_WAVESPEED, &e1);
+  if (st) return st;
+  TileRange tr;
+  tr.tile_start = P->d_tiles[3];
+  const std::vector<int64_t>& pre = P->tiles[3];
+  Tiling tl = P->tl;
+  if (per_grid) {
+    for (int g = 0; g < P->n; ++g) {
+      tr.first = pre[g];
+      tr.count = pre[g + 1] - pre[g];
+      LAUNCH_OR_FAIL(ctx, launch_wavespeed(P->dtype, P->lay, P->work(ctx->flag), buf, tr, s_out,
+                                           blocks_for(ctx, tl, tr.count), L.s));
+    }
+  } else {
+    tr.first = 0;
+    tr.count = pre[P->n];
+    LAUNCH_OR_FAIL(ctx, launch_wavespeed(P->dtype, P->lay, P->work(ctx->flag), buf, tr, s_out,
+                                         blocks_for(ctx, tl, tr.count), L.s));
+  }
+  return L.end(e1);
+}
+
+ripple_fv_status enqueue_dt(ripple_fv_ctx* ctx, Plan* P, Launcher& L, double cfl, double fixed_dt,
+                            int reset_s, double* dt_out) {
+  hipEvent_t e1 = nullptr;
+  ripple_fv_status st = L.begin(RIPPLE_FV_K_DT, &e1);
+  if (st) return st;
+  LAUNCH_OR_FAIL(ctx, launch_dt(P->work(ctx->flag), cfl, fixed_dt, reset_s, dt_out, L.s));
+  return L.end(e1);
+}
+
+// One step starting from buffer `cur`: dt, then x (cur -> oth), y (oth -> cur),
+// z (cur -> oth) with the new state's wave speeds folded into the slots.
+ripple_fv_status enqueue_step(ripple_fv_ctx* ctx, Plan* P, Launcher& L, int cur, double cfl,
+                              double fixed_dt, double* dt_out, bool per_grid) {
+  const int oth = 1 - cur;
+  ripple_fv_status st = enqueue_dt(ctx, P, L, cfl, fixed_dt, 1, dt_out);
+  if (!st) st = enqueue_halo(ctx, P, L, 0, cur);
+  if (!st) st = enqueue_sweep(ctx, P, L, 0, cur, oth, 0, per_grid);
+  if (!st) st = enqueue_halo(ctx, P, L, 1, oth);
+  if (!st) st = enqueue_sweep(ctx, P, L, 1, oth, cur, 0, per_grid);
+  if (!st) st = enqueue_halo(ctx, P, L, 2, cur);
+  if (!st) st = enqueue_sweep(ctx, P, L, 2, cur, oth, 1, per_grid);
+  return st;
+}
+
+ripple_fv_status capture_graph(ripple_fv_ctx* ctx, Plan* P, int nsteps, double cfl, bool per_grid,
+                               hipGraphExec_t* out) {
+  hipStream_t cs = ctx->cap_stream;
+  HIP_OR_FAIL(ctx, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+  Launcher L{ctx, cs, false, {}, 0};
+  ripple_fv_status st = RIPPLE_FV_OK;
+  for (int k = 0; k < nsteps && !st; ++k) st = enqueue_step(ctx, P, L, k & 1, cfl, 0.0, nullptr, per_grid);
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamEndCapture(cs, &graph);
+  if (st) {
+    if (graph) hipGraphDestroy(graph);
+    return st;
+  }
+  if (e != hipSuccess) return fail(ctx, RIPPLE_FV_E_DEVICE, std::string("capture: ") + hipGetErrorString(e));
+  e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+  hipGraphDestroy(graph);
+  if (e != hipSuccess) return fail(ctx, RIPPLE_FV_E_DEVICE, std::string("instantiate: ") + hipGetErrorString(e));
+  return RIPPLE_FV_OK;
+}
+
+ripple_fv_status set_device(ripple_fv_ctx* ctx) {
+  if (!ctx) return RIPPLE_FV_E_INVALID;
+  ctx->err.clear();
+  HIP_OR_FAIL(ctx, hipSetDevice(ctx->device));
+  return RIPPLE_FV_OK;
+}
+
+// Shared body of ripple_fv_run_batch / ripple_fv_step.
+ripple_fv_status run(ripple_fv_ctx* ctx, int n, const ripple_fv_grid* grids, void* const* u_a,
+                     void* const* u_b, int nsteps, double cfl, double fixed_dt, double* dt_out,
+                     int flags, hipStream_t s) {
+  if (nsteps < 0) return fail(ctx, RIPPLE_FV_E_INVALID, "nsteps < 0");
+  if (fixed_dt > 0.0) {
+    if (!std::isfinite(fixed_dt)) return fail(ctx, RIPPLE_FV_E_INVALID, "dt not finite");
+  } else if (!(cfl > 0.0 && cfl <= 1.0)) {
+    return fail(ctx, RIPPLE_FV_E_INVALID, "cfl must be in (0, 1]");
+  }
+  if (std::isnan(fixed_dt)) return fail(ctx, RIPPLE_FV_E_INVALID, "dt is NaN");
+  if (flags & ~(RIPPLE_FV_RUN_GRAPH | RIPPLE_FV_RUN_PER_GRID | RIPPLE_FV_RUN_PROFILE))
+    return fail(ctx, RIPPLE_FV_E_INVALID, "unknown flags");
+  if ((flags & RIPPLE_FV_RUN_GRAPH) && (flags & RIPPLE_FV_RUN_PROFILE))
+    return fail(ctx, RIPPLE_FV_E_INVALID, "GRAPH and PROFILE are exclusive");
+  ripple_fv_status st = validate_batch(ctx, n, grids);
+  if (st) return st;
+  if (!u_a || !u_b) return fail(ctx, RIPPLE_FV_E_INVALID, "NULL buffer list");
+  for (int g = 0; g < n; ++g) {
+    if ((st = ptr_ok(ctx, u_a[g], grids[g].bytes, 256, "u_a"))) return st;
+    if ((st = ptr_ok(ctx, u_b[g], grids[g].bytes, 256, "u_b"))) return st;
+    if (u_a[g] == u_b[g]) return fail(ctx, RIPPLE_FV_E_INVALID, "u_a and u_b alias");
+  }
+  Plan* P = nullptr;
+  if ((st = build_plan(ctx, n, grids, &P))) return st;
+  if ((st = upload_buffers(ctx, P, u_a, u_b, s))) return st;
+  if (nsteps == 0) return RIPPLE_FV_OK;
+  const bool per_grid = flags & RIPPLE_FV_RUN_PER_GRID;
+  Launcher L{ctx, s, (flags & RIPPLE_FV_RUN_PROFILE) != 0, {}, 0};
+  LAUNCH_OR_FAIL(ctx, launch_fill_f64(P->d_t, n, 0.0, s));
+  if (!(fixed_dt > 0.0)) {
+    LAUNCH_OR_FAIL(ctx, launch_fill_u64(P->d_s, 3 * (int64_t)n, 0ull, s));
+    if ((st = enqueue_wavespeed(ctx, P, L, 0, nullptr, per_grid))) return st;
+  }
+  if ((flags & RIPPLE_FV_RUN_GRAPH) && !(fixed_dt > 0.0) && !dt_out) {
+    if (!P->g1 || P->graph_cfl != cfl) {
+      if (P->g1) { hipGraphExecDestroy(P->g1); P->g1 = nullptr; }
+      if (P->g2) { hipGraphExecDestroy(P->g2); P->g2 = nullptr; }
+      if ((st = capture_graph(ctx, P, 1, cfl, per_grid, &P->g1))) return st;
+      if ((st = capture_graph(ctx, P, 2, cfl, per_grid, &P->g2))) return st;
+      P->graph_cfl = cfl;
+    }
+    for (int k = 0; k + 1 < nsteps; k += 2) HIP_OR_FAIL(ctx, hipGraphLaunch(P->g2, s));
+    if (nsteps & 1) HIP_OR_FAIL(ctx, hipGraphLaunch(P->g1, s));
+    return RIPPLE_FV_OK;
+  }
+  for (int k = 0; k < nsteps; ++k) {
+    if ((st = enqueue_step(ctx, P, L, k & 1, cfl, fixed_dt, dt_out, per_grid))) return st;
+  }
+  return L.collect();
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+
+extern "C" {
+
+ripple_fv_status ripple_fv_grid_init(ripple_fv_grid* g) {
+  if (!g) return RIPPLE_FV_E_INVALID;
+  int64_t pitch[3], bytes;
+  std::string why;
+  ripple_fv_status st = grid_check(g, pitch, &bytes, &why);
+  if (st) return st;
+  for (int d = 0; d < 3; ++d) g->pitch[d] = pitch[d];
+  g->bytes = bytes;
+  return RIPPLE_FV_OK;
+}
+
+ripple_fv_status ripple_fv_create(ripple_fv_ctx** out, int32_t device) {
+  if (!out) return RIPPLE_FV_E_INVALID;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess) {
+    (void)hipGetLastError();
+    return RIPPLE_FV_E_DEVICE;
+  }
+  if (device < 0 || device >= count) return RIPPLE_FV_E_INVALID;
+  std::unique_ptr<ripple_fv_ctx> ctx(new ripple_fv_ctx());
+  ctx->device = device;
+  if (hipSetDevice(device) != hipSuccess) return RIPPLE_FV_E_DEVICE;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return RIPPLE_FV_E_DEVICE;
+  ctx->cu_count = prop.multiProcessorCount;
+  if (hipMalloc(&ctx->flag, 256) != hipSuccess) return RIPPLE_FV_E_NOMEM;
+  if (hipMemset(ctx->flag, 0, 256) != hipSuccess) return RIPPLE_FV_E_DEVICE;
+  if (hipMalloc(&ctx->partials, sizeof(double) * DIAG_MAX_BLOCKS * 20) != hipSuccess)
+    return RIPPLE_FV_E_NOMEM;
+  if (hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess)
+    return RIPPLE_FV_E_DEVICE;
+  *out = ctx.release();
+  return RIPPLE_FV_OK;
+}
+
+void ripple_fv_destroy(ripple_fv_ctx* ctx) {
+  if (!ctx) return;
+  hipSetDevice(ctx->device);
+  hipDeviceSynchronize();
+  ctx->plans.clear();
+  for (hipEvent_t e : ctx->events) hipEventDestroy(e);
+  if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
+  if (ctx->partials) hipFree(ctx->partials);
+  if (ctx->flag) hipFree(ctx->flag);
+  delete ctx;
+}
+
+ripple_fv_status ripple_fv_import(ripple_fv_ctx* ctx, const ripple_fv_grid* g, const double* src,
+                                  int32_t variables, void* u, void* stream) {
+  ripple_fv_status st = set_device(ctx);
+  if (st) return st;
+  if ((st = grid_ok(ctx, g))) return st;
+  if (variables != RIPPLE_FV_PRIMITIVE && variables != RIPPLE_FV_CONSERVED)
+    return fail(ctx, RIPPLE_FV_E_INVALID, "unknown variables kind");
+  const int64_t ncell = (int64_t)g->n[0] * g->n[1] * g->n[2];
+  if ((st = ptr_ok(ctx, src, ncell * 5 * 8, 8, "src"))) return st;
+  if ((st = ptr_ok(ctx, u, g->bytes, 256, "u"))) return st;
+  HIP_OR_FAIL(ctx, launch_import(desc_of(*g, u), src, variables == RIPPLE_FV_PRIMITIVE,
+                                 (hipStream_t)stream));
+  return RIPPLE_FV_OK;
+}
+
+ripple_fv_status ripple_fv_export(ripple_fv_ctx* ctx, const ripple_fv_grid* g, const void* u,
+                                  double* dst, void* stream) {
+  ripple_fv_status st = set_device(ctx);
+  if (st) return st;
+  if ((st = grid_ok(ctx, g))) return st;
+  const int64_t ncell = (int64_t)g->n[0] * g->n[1] * g->n[2];
+  if ((st = ptr_ok(ctx, u, g->bytes, 256, "u"))) return st;
+  if ((st = ptr_ok(ctx, dst, ncell * 5 * 8, 8, "dst"))) return st;
+  HIP_OR_FAIL(ctx, launch_export(desc_of(*g, u), dst, (hipStream_t)stream));
+  return RIPPLE_FV_OK;
+}
+
+ripple_fv_status ripple_fv_convert(ripple_fv_ctx* ctx, const ripple_fv_grid* gs, const void* src,
+                                   const ripple_fv_grid* gd, void* dst, void* stream) {
+  ripple_fv_status st = set_device(ctx);
+  if (st) return st;
+  if ((st = grid_ok(ctx, gs)) || (st = grid_ok(ctx, gd))) return st;
+  for (int d = 0; d < 3; ++d)
+    if (gs->n[d] != gd->n[d]) return fail(ctx, RIPPLE_FV_E_INVALID, "extents differ");
+  if ((st = ptr_ok(ctx, src, gs->bytes, 256, "src"))) return st;
+  if ((st = ptr_ok(ctx, dst, gd->bytes, 256, "dst"))) return st;
+  if (src == dst) return fail(ctx, RIPPLE_FV_E_INVALID, "src and dst alias");
+  HIP_OR_FAIL(ctx, launch_convert(desc_of(*gs, src), desc_of(*gd, dst), (hipStream_t)stream));
+  return RIPPLE_FV_OK;
+}
+
+ripple_fv_status ripple_fv_max_wavespeed(ripple_fv_ctx* ctx, const ripple_fv_grid* g,
+                                         const void* u, double* s_dev, void* stream) {
+  ripple_fv_status st = set_device(ctx);
+  if (st) return st;
+  if ((st = grid_ok(ctx, g))) return st;
+  if ((st = ptr_ok(ctx, u, g->bytes, 256, "u"))) return st;
+  if ((st = ptr_ok(ctx, s_dev, 24, 8, "s_dev"))) return st;
+  ripple_fv_grid one = *g;
+  one.group = -1;
+  for (int f = 0; f < 6; ++f) one.nbr[f] = -1;
+  Plan* P = nullptr;
+  if ((st = build_plan(ctx, 1, &one, &P))) return st;
+  void* a[1] = {const_cast<void*>(u)};
+  hipStream_t s = (hipStream_t)stream;
+  if ((st = upload_buffers(ctx, P, a, nullptr, s))) return st;
+  unsigned long long* out = reinterpret_cast<unsigned long long*>(s_dev);
+  HIP_OR_FAIL(ctx, launch_fill_u64(out, 3, 0ull, s));
+  Launcher L{ctx, s, false, {}, 0};
+  return enqueue_wavespeed(ctx, P, L, 0, out, false);
+}
+
+ripple_fv_status ripple_fv_sweep(ripple_fv_ctx* ctx, const ripple_fv_grid* g, int32_t axis,
+                                 const void* u_in, void* u_out, double dt, void* stream) {
+  ripple_fv_status st = set_device(ctx);
+  if (st) return st;
+  if ((st = grid_ok(ctx, g))) return st;
+  if (axis < 0 || axis > 2) return fail(ctx, RIPPLE_FV_E_INVALID, "axis must be 0, 1 or 2");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(ctx, RIPPLE_FV_E_INVALID, "dt must be > 0");
+  if ((st = ptr_ok(ctx, u_in, g->bytes, 256, "u_in"))) return st;
+  if ((st = ptr_ok(ctx, u_out, g->bytes, 256, "u_out"))) return st;
+  if (u_in == u_out) return fail(ctx, RIPPLE_FV_E_INVALID, "u_in and u_out alias");
+  // Linked faces read u_in's padding: keep them as halo faces (a self link
+  // marks them; the sweep itself copies nothing).
+  ripple_fv_grid one = *g;
+  one.group = -1;
+  for (int f = 0; f < 6; ++f) one.nbr[f] = one.nbr[f] >= 0 ? 0 : -1;
+  Plan* P = nullptr;
+  if ((st = build_plan(ctx, 1, &one, &P))) return st;
+  void* a[1] = {const_cast<void*>(u_in)};
+  void* b[1] = {u_out};
+  hipStream_t s = (hipStream_t)stream;
+  if ((st = upload_buffers(ctx, P, a, b, s))) return st;
+  Launcher L{ctx, s, false, {}, 0};
+  if ((st = enqueue_dt(ctx, P, L, 1.0, dt, 0, nullptr))) return st;
+  return enqueue_sweep(ctx, P, L, axis, 0, 1, 0, false);
+}
+
+ripple_fv_status ripple_fv_step(ripple_fv_ctx* ctx, const ripple_fv_grid* g, void* u_in,
+                                void* u_out, double cfl, double dt, double* dt_dev,
+                                void* stream) {
+  ripple_fv_status st = set_device(ctx);
+  if (st) return st;
+  if ((st = grid_ok(ctx, g))) return st;
+  for (int f = 0; f < 6; ++f)
+    if (g->nbr[f] >= 0)
+      return fail(ctx, RIPPLE_FV_E_INVALID, "ripple_fv_step takes a whole grid; use run_batch for sub-blocks");
+  if (dt_dev && (st = ptr_ok(ctx, dt_dev, 8, 8, "dt_dev"))) return st;
+  ripple_fv_grid one = *g;
+  one.group = -1;
+  void* a[1] = {u_in};
+  void* b[1] = {u_out};
+  return run(ctx, 1, &one, a, b, 1, cfl, dt, dt_dev, 0, (hipStream_t)stream);
+}
+
+ripple_fv_status ripple_fv_run_batch(ripple_fv_ctx* ctx, int32_t n, const ripple_fv_grid* grids,
+                                     void* const* u_a, void* const* u_b, int32_t nsteps,
+                                     double cfl, int32_t flags, void* stream) {
+  ripple_fv_status st = set_device(ctx);
+  if (st) return st;
+  return run(ctx, n, grids, u_a, u_b, nsteps, cfl, 0.0, nullptr, flags, (hipStream_t)stream);
+}
+
+ripple_fv_status ripple_fv_batch_time(ripple_fv_ctx* ctx, int32_t n, const ripple_fv_grid* grids,
+                                      double* t_host, double* dt_host) {
+  ripple_fv_status st = set_device(ctx);
+  if (st) return st;
+  if (n < 1 || !grids || !t_host) return fail(ctx, RIPPLE_FV_E_INVALID, "bad arguments");
+  auto it = ctx->plans.find(plan_key(n, grids));
+  if (it == ctx->plans.end()) return fail(ctx, RIPPLE_FV_E_INVALID, "no run for these grids");
+  Plan* P = it->second.get();
+  HIP_OR_FAIL(ctx, hipDeviceSynchronize());
+  HIP_OR_FAIL(ctx, hipMemcpy(t_host, P->d_t, sizeof(double) * n, hipMemcpyDeviceToHost));
+  if (dt_host) HIP_OR_FAIL(ctx, hipMemcpy(dt_host, P->d_dt, sizeof(double) * n, hipMemcpyDeviceToHost));
+  return RIPPLE_FV_OK;
+}
+
+ripple_fv_status ripple_fv_partition(const ripple_fv_grid* whole, const int32_t parts[3],
+                                     int32_t first_index, ripple_fv_grid* sub) {
+  if (!whole || !parts || !sub || first_index < 0) return RIPPLE_FV_E_INVALID;
+  int64_t pitch[3], bytes;
+  std::string why;
+  if (grid_check(whole, pitch, &bytes, &why)) return RIPPLE_FV_E_INVALID;
+  for (int d = 0; d < 3; ++d)
+    if (parts[d] < 1 || whole->n[d] / parts[d] < 2) return RIPPLE_FV_E_INVALID;
+  for (int d = 0; d < 3; ++d)
+    if (whole->nbr[d * 2] >= 0 || whole->nbr[d * 2 + 1] >= 0) return RIPPLE_FV_E_INVALID;
+  const int px = parts[0], py = parts[1], pz = parts[2];
+  auto idx = [&](int a, int b, int c) { return first_index + a + px * (b + py * c); };
+  int p3[3] = {px, py, pz};
+  for (int c = 0; c < pz; ++c)
+    for (int b = 0; b < py; ++b)
+      for (int a = 0; a < px; ++a) {
+        ripple_fv_grid& S = sub[a + px * (b + py * c)];
+        S = *whole;
+        const int coord[3] = {a, b, c};
+        for (int d = 0; d < 3; ++d) {
+          const int nn = whole->n[d], k = coord[d], np = p3[d];
+          S.n[d] = nn / np + (k < nn % np ? 1 : 0);
+          for (int side = 0; side < 2; ++side) {
+            int nb[3] = {a, b, c};
+            nb[d] += side == 0 ? -1 : 1;
+            const bool inside = nb[d] >= 0 && nb[d] < np;
+            if (!inside && whole->bc[d] == RIPPLE_FV_PERIODIC) nb[d] = (nb[d] + np) % np;
+            S.nbr[2 * d + side] =
+                (inside || whole->bc[d] == RIPPLE_FV_PERIODIC) ? idx(nb[0], nb[1], nb[2]) : -1;
+          }
+        }
+        S.group = first_index;
+        if (ripple_fv_grid_init(&S)) return RIPPLE_FV_E_INVALID;
+      }
+  return RIPPLE_FV_OK;
+}
+
+ripple_fv_status ripple_fv_halo_exchange(ripple_fv_ctx* ctx, int32_t n,
+                                         const ripple_fv_grid* grids, void* const* u,
+                                         int32_t axis, void* stream) {
+  ripple_fv_status st = set_device(ctx);
+  if (st) return st;
+  if (axis < 0 || axis > 2) return fail(ctx, RIPPLE_FV_E_INVALID, "axis must be 0, 1 or 2");
+  if ((st = validate_batch(ctx, n, grids))) return st;
+  if (!u) return fail(ctx, RIPPLE_FV_E_INVALID, "NULL buffer list");
+  for (int g = 0; g < n; ++g)
+    if ((st = ptr_ok(ctx, u[g], grids[g].bytes, 256, "u"))) return st;
+  Plan* P = nullptr;
+  if ((st = build_plan(ctx, n, grids, &P))) return st;
+  hipStream_t s = (hipStream_t)stream;
+  if ((st = upload_buffers(ctx, P, u, u, s))) return st;
+  Launcher L{ctx, s, false, {}, 0};
+  return enqueue_halo(ctx, P, L, axis, 0);
+}
+
+ripple_fv_status ripple_fv_conserved_sums(ripple_fv_ctx* ctx, const ripple_fv_grid* g,
+                                          const void* u, double* sums_dev, void* stream) {
+  ripple_fv_status st = set_device(ctx);
+  if (st) return st;
+  if ((st = grid_ok(ctx, g))) return st;
+  if ((st = ptr_ok(ctx, u, g->bytes, 256, "u"))) return st;
+  if ((st = ptr_ok(ctx, sums_dev, 40, 8, "sums_dev"))) return st;
+  const int64_t ncell = (int64_t)g->n[0] * g->n[1] * g->n[2];
+  const int nb = (int)std::min<int64_t>(DIAG_MAX_BLOCKS, (ncell + DIAG_BLOCK - 1) / DIAG_BLOCK);
+  HIP_OR_FAIL(ctx, launch_sums(desc_of(*g, u), ctx->partials, nb, sums_dev, (hipStream_t)stream));
+  return RIPPLE_FV_OK;
+}
+
+ripple_fv_status ripple_fv_error_norms(ripple_fv_ctx* ctx, const ripple_fv_grid* g,
+                                       const void* u, const double* ref_dev, double* out_dev,
+                                       void* stream) {
+  ripple_fv_status st = set_device(ctx);
+  if (st) return st;
+  if ((st = grid_ok(ctx, g))) return st;
+  const int64_t ncell = (int64_t)g->n[0] * g->n[1] * g->n[2];
+  if ((st = ptr_ok(ctx, u, g->bytes, 256, "u"))) return st;
+  if ((st = ptr_ok(ctx, ref_dev, ncell * 40, 8, "ref_dev"))) return st;
+  if ((st = ptr_ok(ctx, out_dev, 160, 8, "out_dev"))) return st;
+  const int nb = (int)std::min<int64_t>(DIAG_MAX_BLOCKS, (ncell + DIAG_BLOCK - 1) / DIAG_BLOCK);
+  HIP_OR_FAIL(ctx, launch_norms(desc_of(*g, u), ref_dev, ctx->partials, nb, out_dev,
+                                (hipStream_t)stream));
+  return RIPPLE_FV_OK;
+}
+
+ripple_fv_status ripple_fv_check(ripple_fv_ctx* ctx) {
+  ripple_fv_status st = set_device(ctx);
+  if (st) return st;
+  HIP_OR_FAIL(ctx, hipDeviceSynchronize());
+  unsigned int flag = 0;
+  HIP_OR_FAIL(ctx, hipMemcpy(&flag, ctx->flag, sizeof(flag), hipMemcpyDeviceToHost));
+  if (flag) {
+    const unsigned int zero = 0;
+    HIP_OR_FAIL(ctx, hipMemcpy(ctx->flag, &zero, sizeof(zero), hipMemcpyHostToDevice));
+    return fail(ctx, RIPPLE_FV_E_NONPHYSICAL, "non-physical state (rho <= 0, p <= 0 or non-finite)");
+  }
+  return RIPPLE_FV_OK;
+}
+
+ripple_fv_status ripple_fv_profile(ripple_fv_ctx* ctx, double* ms, int64_t* launches) {
+  if (!ctx || !ms || !launches) return RIPPLE_FV_E_INVALID;
+  for (int k = 0; k < RIPPLE_FV_NKERNELS; ++k) {
+    ms[k] = ctx->prof_ms[k];
+    launches[k] = ctx->prof_n[k];
+    ctx->prof_ms[k] = 0.0;
+    ctx->prof_n[k] = 0;
+  }
+  return RIPPLE_FV_OK;
+}
+
+const char* ripple_fv_status_string(ripple_fv_status s) {
+  switch (s) {
+    case RIPPLE_FV_OK: return "ok";
+    case RIPPLE_FV_E_INVALID: return "invalid argument";
+    case RIPPLE_FV_E_UNSUPPORTED: return "unsupported";
+    case RIPPLE_FV_E_DEVICE: return "HIP error";
+    case RIPPLE_FV_E_NONPHYSICAL: return "non-physical state";
+    case RIPPLE_FV_E_NOMEM: return "out of memory";
+    default: return "unknown status";
+  }
+}
+
+const char* ripple_fv_last_error(ripple_fv_ctx* ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Autotuner
+// ---------------------------------------------------------------------------
+
+namespace {
+
+struct TuneBufs {
+  std::vector<void*> a, b;
+  ~TuneBufs() {
+    for (void* p : a) if (p) hipFree(p);
+    for (void* p : b) if (p) hipFree(p);
+  }
+};
+
+// Time `steps` steps of the batch described by `cand` on a synthetic smooth
+// state; returns milliseconds (or a status through *st).
+double time_candidate(ripple_fv_ctx* ctx, std::vector<ripple_fv_grid>& cand, double* W,
+                      hipStream_t s, ripple_fv_status* st) {
+  *st = RIPPLE_FV_OK;
+  const int n = (int)cand.size();
+  for (auto& g : cand) {
+    if (ripple_fv_grid_init(&g)) { *st = fail(ctx, RIPPLE_FV_E_INVALID, "tuner candidate"); return 0; }
+  }
+  TuneBufs B;
+  B.a.assign(n, nullptr);
+  B.b.assign(n, nullptr);
+  for (int g = 0; g < n; ++g) {
+    if (hipMalloc(&B.a[g], cand[g].bytes) != hipSuccess || hipMalloc(&B.b[g], cand[g].bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      *st = fail(ctx, RIPPLE_FV_E_NOMEM, "tuner buffer allocation failed");
+      return 0;
+    }
+    hipError_t e = launch_tune_state(W, cand[g].n, s);
+    if (e == hipSuccess) e = launch_import(desc_of(cand[g], B.a[g]), W, 1, s);
+    if (e != hipSuccess) { *st = fail(ctx, RIPPLE_FV_E_DEVICE, hipGetErrorString(e)); return 0; }
+  }
+  if ((*st = run(ctx, n, cand.data(), B.a.data(), B.b.data(), 1, 0.9, 0.0, nullptr, 0, s))) return 0;
+  hipEvent_t e0, e1;
+  hipEventCreate(&e0);
+  hipEventCreate(&e1);
+  hipEventRecord(e0, s);
+  *st = run(ctx, n, cand.data(), B.a.data(), B.b.data(), 3, 0.9, 0.0, nullptr, 0, s);
+  hipEventRecord(e1, s);
+  hipEventSynchronize(e1);
+  float ms = 0.f;
+  hipEventElapsedTime(&ms, e0, e1);
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  hipDeviceSynchronize();
+  // drop the candidate's plan: its buffers are about to be freed
+  ctx->plans.erase(plan_key(n, cand.data()));
+  for (auto it = ctx->plan_order.begin(); it != ctx->plan_order.end(); ++it)
+    if (*it == plan_key(n, cand.data())) { ctx->plan_order.erase(it); break; }
+  return ms;
+}
+
+}  // namespace
+
+extern "C" ripple_fv_status ripple_fv_batch_tune(ripple_fv_ctx* ctx, int32_t n,
+                                                 const ripple_fv_grid* in,
+                                                 ripple_fv_grid* chosen, void* stream) {
+  ripple_fv_status st = set_device(ctx);
+  if (st) return st;
+  if (n < 1 || !in || !chosen) return fail(ctx, RIPPLE_FV_E_INVALID, "bad arguments");
+  std::vector<ripple_fv_grid> base(in, in + n);
+  for (auto& g : base) {
+    g.layout = RIPPLE_FV_SOA;
+    g.aosoa_w = 0;
+    g.x_block = g.yz_block = g.yz_segment = g.persist = 0;
+    if (ripple_fv_grid_init(&g)) return fail(ctx, RIPPLE_FV_E_INVALID, "bad grid descriptor");
+  }
+  if ((st = validate_batch(ctx, n, base.data()))) return st;
+  const std::string key = plan_key(n, base.data());
+  auto hit = ctx->tune_cache.find(key);
+  if (hit != ctx->tune_cache.end()) {
+    std::copy(hit->second.begin(), hit->second.end(), chosen);
+    return RIPPLE_FV_OK;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  int64_t max_cell = 0;
+  for (auto& g : base) max_cell = std::max<int64_t>(max_cell, (int64_t)g.n[0] * g.n[1] * g.n[2]);
+  double* W = nullptr;
+  if (hipMalloc(&W, sizeof(double) * 5 * max_cell) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(ctx, RIPPLE_FV_E_NOMEM, "tuner state allocation failed");
+  }
+  std::vector<ripple_fv_grid> best = base;
+  double best_ms = 1e300;
+  auto consider = [&](std::vector<ripple_fv_grid> cand) -> ripple_fv_status {
+    ripple_fv_status s2;
+    const double ms = time_candidate(ctx, cand, W, s, &s2);
+    if (s2) return s2;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = cand;
+    }
+    return RIPPLE_FV_OK;
+  };
+  auto with = [&](auto edit) {
+    std::vector<ripple_fv_grid> c = best;
+    for (auto& g : c) edit(g);
+    return c;
+  };
+  // 1. layout
+  const int layouts[5][2] = {{RIPPLE_FV_SOA, 0}, {RIPPLE_FV_AOS, 0}, {RIPPLE_FV_AOSOA, 16},
+                             {RIPPLE_FV_AOSOA, 32}, {RIPPLE_FV_AOSOA, 64}};
+  std::vector<ripple_fv_grid> start = best;
+  for (auto& L : layouts) {
+    std::vector<ripple_fv_grid> c = start;
+    for (auto& g : c) { g.layout = L[0]; g.aosoa_w = L[1]; }
+    if ((st = consider(c))) break;
+  }
+  // 2. x sweep workgroup
+  for (int xb : {128, 256}) {
+    if (st) break;
+    st = consider(with([&](ripple_fv_grid& g) { g.x_block = xb; }));
+  }
+  // 3. y/z sweep chunk width and segment length
+  for (int yb : {64, 128, 256})
+    for (int sg : {16, 32, 64, 128}) {
+      if (st) break;
+      st = consider(with([&](ripple_fv_grid& g) { g.yz_block = yb; g.yz_segment = sg; }));
+    }
+  // 4. persistent launches
+  for (int pc : {0, 2, 4, 8}) {
+    if (st) break;
+    st = consider(with([&](ripple_fv_grid& g) { g.persist = pc; }));
+  }
+  hipFree(W);
+  if (st) return st;
+  for (auto& g : best) ripple_fv_grid_init(&g);
+  ctx->tune_cache[key] = best;
+  std::copy(best.begin(), best.end(), chosen);
+  return RIPPLE_FV_OK;
+}

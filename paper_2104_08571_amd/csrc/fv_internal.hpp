@@ -1,0 +1,117 @@
+// Internal declarations shared by the kernel and C-ABI translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ripple_fv.h"
+
+namespace rfv {
+
+constexpr int NV = RIPPLE_FV_NVAR;
+constexpr int HALO = RIPPLE_FV_HALO;
+
+// Storage layouts as compiled kernel variants.
+enum Lay : int { LAY_AOS = 0, LAY_SOA = 1, LAY_AOSOA16 = 2, LAY_AOSOA32 = 3, LAY_AOSOA64 = 4,
+                 LAY_COUNT = 5 };
+
+// Face treatment for a sweep: physical boundary condition or padding filled
+// from a neighbouring sub-block.
+enum FaceMode : int { FACE_TRANSMISSIVE = 0, FACE_PERIODIC = 1, FACE_HALO = 2 };
+
+// Device copy of one grid of a batch.  Read by every kernel through a
+// wave-uniform index, so the compiler keeps it in scalar registers.
+struct DevGrid {
+  void* buf[2];        // state buffers A (initial) and B
+  int32_t n[3];        // interior extents
+  int32_t mode[6];     // FaceMode per face (-x, +x, -y, +y, -z, +z)
+  int64_t px, pxy;     // padded pitch of a row and of a plane, in cells
+  int64_t ptot;        // padded cells per buffer
+  double dx[3];
+  int32_t group;       // index of the grid whose wave-speed slot and dt this grid uses
+  int32_t pad_;
+};
+
+// Per-batch device workspace handed to the kernels.
+struct Work {
+  const DevGrid* grids;
+  int32_t ngrids;
+  int32_t pad_;
+  double* lam;                     // [ngrids * 3] dt / dx_d
+  double* t;                       // [ngrids] time reached
+  double* dt;                      // [ngrids] last dt
+  unsigned long long* s_acc;       // [ngrids * 3] wave-speed maxima (double bits), by group
+  unsigned int* flag;              // sticky non-physical flag
+};
+
+// Tiles of one sweep: tile_start[g] is the first tile of grid g, tile_start[ngrids]
+// the total.  A launch processes tiles [first, first + count).
+struct TileRange {
+  const int64_t* tile_start;
+  int64_t first;
+  int64_t count;
+};
+
+struct SweepParams {
+  Work w;
+  TileRange tiles;
+  int32_t in, out;     // buffer index read / written
+  int32_t seg;         // cells per thread along the sweep axis (y, z sweeps)
+  int32_t fuse_s;      // accumulate wave speeds of the output (z sweep)
+};
+
+struct HaloTask {
+  int32_t dst, src;    // grid indices
+  int32_t side;        // 0: dst face -axis <- src high interior; 1: dst face +axis <- src low interior
+  int32_t pad_;
+};
+
+// Tiling knobs resolved from a descriptor (defaults applied).
+struct Tiling {
+  int x_block;     // threads per workgroup of the x sweep (128 or 256)
+  int yz_block;    // lanes per workgroup of the y/z sweeps (64, 128, 256)
+  int yz_segment;  // cells per thread along y/z
+  int persist;     // workgroups per CU for persistent launches, 0 = one per tile
+};
+
+int lay_of(const ripple_fv_grid& g);
+
+// Tile counts of one grid (must match the kernels' decoding).
+int64_t tiles_x(const ripple_fv_grid& g, int x_block);
+int64_t tiles_yz(const ripple_fv_grid& g, int axis, int yz_block, int yz_segment);
+int64_t tiles_ws(const ripple_fv_grid& g);
+constexpr int WS_BLOCK = 256;
+constexpr int WS_CELLS_PER_THREAD = 4;
+
+// Kernel launchers (return hipError_t of the launch).
+hipError_t launch_sweep(int dtype, int lay, int axis, const Tiling& tl, const SweepParams& p,
+                        int grid_blocks, hipStream_t s);
+hipError_t launch_wavespeed(int dtype, int lay, const Work& w, int in, TileRange tr,
+                            unsigned long long* s_out, int grid_blocks, hipStream_t s);
+hipError_t launch_dt(const Work& w, double cfl, double fixed_dt, int reset_s, double* dt_out,
+                     hipStream_t s);
+hipError_t launch_halo(int dtype, int lay, const Work& w, int buf, int axis, const HaloTask* tasks,
+                       int ntasks, int64_t max_area, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s);
+hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t s);
+
+// Generic (runtime layout) transfer and diagnostics kernels.
+struct Desc {
+  void* buf;
+  int32_t n[3];
+  int32_t lay;
+  int32_t dtype;
+  int32_t pad_;
+  int64_t px, pxy, ptot;
+};
+hipError_t launch_import(const Desc& d, const double* src, int primitive, hipStream_t s);
+hipError_t launch_export(const Desc& d, double* dst, hipStream_t s);
+hipError_t launch_convert(const Desc& src, const Desc& dst, hipStream_t s);
+hipError_t launch_tune_state(double* W, const int n[3], hipStream_t s);
+hipError_t launch_sums(const Desc& d, double* partials, int nblocks, double* out, hipStream_t s);
+hipError_t launch_norms(const Desc& d, const double* ref, double* partials, int nblocks,
+                        double* out, hipStream_t s);
+constexpr int DIAG_BLOCK = 256;
+constexpr int DIAG_MAX_BLOCKS = 1024;
+
+}  // namespace rfv

@@ -1,0 +1,717 @@
+// HIP kernels for gfx950: the split finite-volume Euler step and its helpers.
+//
+// Hot kernels (templated on precision and layout):
+//  - k_sweep_x   : update along x.  A workgroup stages a chunk of consecutive
+//                  cells of the flattened (row, x) index space -- every
+//                  interior row followed by its padding columns -- in LDS, so
+//                  global loads and stores are contiguous runs of memory and
+//                  the x stencil is read from LDS.
+//  - k_sweep_yz  : update along y or z.  Lanes cover consecutive cells of the
+//                  plane across the sweep (coalesced), and each thread marches
+//                  along the sweep axis with a five-cell register window, so
+//                  every cell is read once per sweep (plus 4 cells per segment).
+//                  The z sweep can also reduce the new state's wave speeds
+//                  for the next step's time step.
+//  - k_wavespeed : per-cell |u_d| + c and the max over each grid.
+//  - k_dt        : time step per grid from the maxima (kept on the device so a
+//                  captured step loop needs no host round trip).
+//  - k_halo      : copies two interior layers of a sub-block into its
+//                  neighbour's padding.
+// Physical boundaries are applied while loading (transmissive = clamp to the
+// edge cell, periodic = wrap), so no pass over the padding is needed; faces
+// linked to a neighbouring sub-block read the padding that k_halo filled.
+#include <hip/hip_runtime.h>
+
+#include "fv_internal.hpp"
+#include "fv_layout.hpp"
+#include "fv_math.hpp"
+
+namespace rfv {
+
+// ---------------------------------------------------------------------------
+// Tile bookkeeping
+// ---------------------------------------------------------------------------
+
+// Workgroups are dispatched round-robin over the 8 XCDs.  Renumber them so
+// that each XCD takes one contiguous run of tiles: neighbouring tiles share
+// halo cells and then share that XCD's L2.
+__device__ __forceinline__ int64_t xcd_order(int64_t b, int64_t nblocks) {
+  const int64_t x = b & 7, k = b >> 3, q = nblocks >> 3, r = nblocks & 7;
+  return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
+// Grid owning global tile t: the last g with tile_start[g] <= t.
+__device__ __forceinline__ int find_grid(const int64_t* start, int n, int64_t t) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (start[mid] <= t) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Interior index to load for position j (may lie in [-2, n+1]) along an axis:
+// transmissive faces clamp, periodic faces wrap, halo faces read the padding.
+__device__ __forceinline__ int face_index(int j, int n, int mode_lo, int mode_hi) {
+  if (j < 0) return mode_lo == FACE_TRANSMISSIVE ? 0 : (mode_lo == FACE_PERIODIC ? j + n : j);
+  if (j >= n) return mode_hi == FACE_TRANSMISSIVE ? n - 1 : (mode_hi == FACE_PERIODIC ? j - n : j);
+  return j;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = __builtin_fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Reduce per-thread wave-speed maxima over the workgroup and fold them into
+// the group's slot.  The global maximum only grows, so a tile whose maximum
+// does not exceed the value already seen skips the atomic.
+template <typename T>
+__device__ __forceinline__ void fold_wavespeeds(T s[3], bool bad, unsigned long long* slot,
+                                                unsigned int* flag, T* lds /* 3 * 16 */) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+  if (bad) *flag = 1u;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) s[d] = wave_max(s[d]);
+  if (lane == 0) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) lds[wave * 3 + d] = s[d];
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    T m = lds[threadIdx.x];
+    for (int wv = 1; wv < nwave; ++wv) m = __builtin_fmax(m, lds[wv * 3 + threadIdx.x]);
+    const unsigned long long bits = __double_as_longlong((double)m);
+    if (bits > __atomic_load_n(&slot[threadIdx.x], __ATOMIC_RELAXED))
+      atomicMax(&slot[threadIdx.x], bits);
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// x sweep
+// ---------------------------------------------------------------------------
+
+// Chunk of NT consecutive positions of the flattened (row, x) space, rows
+// being the interior (j, k) pairs and positions within a row running over
+// x = -2 .. n0+1 (the padded columns).  Thread t holds position
+// P0 - 2 + t; threads 2 .. NT-3 write the interior cells among them, so each
+// chunk produces up to NT - 4 cells and overlaps its neighbours by 4.
+template <typename T, int LAY, int NT>
+__global__ void __launch_bounds__(NT) k_sweep_x(SweepParams p) {
+  constexpr int C = NT - 4;
+  __shared__ T sA[5][NT];
+  __shared__ T sB[5][NT];
+  const int tid = threadIdx.x;
+  for (int64_t b = xcd_order(blockIdx.x, gridDim.x); b < p.tiles.count; b += gridDim.x) {
+    const int64_t gt = p.tiles.first + b;
+    const int g = find_grid(p.tiles.tile_start, p.w.ngrids, gt);
+    const DevGrid& G = p.w.grids[g];
+    const int64_t lt = gt - p.tiles.tile_start[g];
+    const int nx = G.n[0], ny = G.n[1];
+    const uint32_t lx = (uint32_t)(nx + 4);
+    const int64_t total = (int64_t)lx * ny * G.n[2];
+    const int64_t f = lt * C - 2 + tid;
+    const bool valid = f >= 0 && f < total;
+    const uint32_t fc = (uint32_t)(f < 0 ? 0 : (f >= total ? total - 1 : f));
+    const uint32_t row = fc / lx;
+    const int il = (int)(fc - row * lx);             // padded x index
+    const int j = (int)(row % (uint32_t)ny);
+    const int k = (int)(row / (uint32_t)ny);
+    const int i = face_index(il - 2, nx, G.mode[0], G.mode[1]);
+    const int64_t rowq = (int64_t)(k + 2) * G.pxy + (int64_t)(j + 2) * G.px;
+    const T lam = (T)p.w.lam[g * 3 + 0];
+    const T hl = T(0.5) * lam;
+
+    T u[5];
+    load_cell<T, LAY>(G.buf[p.in], rowq + i + 2, G.ptot, u);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) sA[c][tid] = u[c];
+    __syncthreads();
+
+    T bl[5], br[5];
+    if (tid >= 1 && tid <= NT - 2) {
+      T dm[5], dp[5];
+#pragma unroll
+      for (int c = 0; c < 5; ++c) {
+        dm[c] = u[c] - sA[c][tid - 1];
+        dp[c] = sA[c][tid + 1] - u[c];
+      }
+      hancock<T, 0>(u, dm, dp, hl, bl, br);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 5; ++c) sA[c][tid] = br[c];
+    __syncthreads();
+
+    T fx[5];
+    if (tid >= 2 && tid <= NT - 2) {
+      T left[5];
+#pragma unroll
+      for (int c = 0; c < 5; ++c) left[c] = sA[c][tid - 1];
+      hllc<T, 0>(left, bl, fx);   // face between positions tid-1 and tid
+#pragma unroll
+      for (int c = 0; c < 5; ++c) sB[c][tid] = fx[c];
+    }
+    __syncthreads();
+    if (tid >= 2 && tid <= NT - 3 && valid && il >= 2 && il < nx + 2) {
+      T o[5];
+#pragma unroll
+      for (int c = 0; c < 5; ++c) o[c] = u[c] - lam * (sB[c][tid + 1] - fx[c]);
+      store_cell<T, LAY>(G.buf[p.out], rowq + il, G.ptot, o);
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// y / z sweeps
+// ---------------------------------------------------------------------------
+
+// Tile = (chunk of blockDim.x consecutive cells of the plane across the sweep,
+// x fastest) x (segment of p.seg cells along D).  Segment index runs fastest
+// so that the segments of one column, which overlap by four cells, are
+// processed by neighbouring workgroups.
+template <typename T, int LAY, int D>
+__global__ void __launch_bounds__(256) k_sweep_yz(SweepParams p) {
+  __shared__ T red[3 * 16];
+  const int nt = blockDim.x;
+  const int tid = threadIdx.x;
+  for (int64_t b = xcd_order(blockIdx.x, gridDim.x); b < p.tiles.count; b += gridDim.x) {
+    const int64_t gt = p.tiles.first + b;
+    const int g = find_grid(p.tiles.tile_start, p.w.ngrids, gt);
+    const DevGrid& G = p.w.grids[g];
+    const int64_t lt = gt - p.tiles.tile_start[g];
+    const int na = G.n[0];
+    const int nb = G.n[D == 1 ? 2 : 1];
+    const int nd = G.n[D];
+    const int nseg = (nd + p.seg - 1) / p.seg;
+    const int64_t chunk = lt / nseg;
+    const int s = (int)(lt - chunk * nseg);
+    const uint32_t nplane = (uint32_t)na * (uint32_t)nb;
+    const uint32_t fl = (uint32_t)(chunk * nt + tid);
+    const bool active = fl < nplane;
+    const uint32_t fc = active ? fl : nplane - 1;
+    const int ia = (int)(fc % (uint32_t)na);
+    const int ib = (int)(fc / (uint32_t)na);
+    const int64_t stride = D == 1 ? G.px : G.pxy;
+    const int64_t base = (int64_t)(ia + 2) + (int64_t)(ib + 2) * (D == 1 ? G.pxy : G.px);
+    const int mlo = G.mode[2 * D], mhi = G.mode[2 * D + 1];
+    const void* src = G.buf[p.in];
+    void* dst = G.buf[p.out];
+    const T lam = (T)p.w.lam[g * 3 + D];
+    const T hl = T(0.5) * lam;
+    const int j0 = s * p.seg;
+    const int len = min(p.seg, nd - j0);
+
+    T w0[5], w1[5], w2[5], dprev[5], dnext[5], bl[5], br[5], brp[5], fprev[5];
+    load_cell<T, LAY>(src, base + (face_index(j0 - 2, nd, mlo, mhi) + 2) * stride, G.ptot, w0);
+    load_cell<T, LAY>(src, base + (face_index(j0 - 1, nd, mlo, mhi) + 2) * stride, G.ptot, w1);
+    load_cell<T, LAY>(src, base + (face_index(j0, nd, mlo, mhi) + 2) * stride, G.ptot, w2);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      dprev[c] = w1[c] - w0[c];
+      dnext[c] = w2[c] - w1[c];
+    }
+    hancock<T, D>(w1, dprev, dnext, hl, bl, brp);          // cell j0 - 1
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      w0[c] = w1[c];
+      w1[c] = w2[c];
+      dprev[c] = dnext[c];
+    }
+    load_cell<T, LAY>(src, base + (face_index(j0 + 1, nd, mlo, mhi) + 2) * stride, G.ptot, w2);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) dnext[c] = w2[c] - w1[c];
+    hancock<T, D>(w1, dprev, dnext, hl, bl, br);           // cell j0
+    hllc<T, D>(brp, bl, fprev);                            // face j0 - 1/2
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      brp[c] = br[c];
+      w0[c] = w1[c];
+      w1[c] = w2[c];
+      dprev[c] = dnext[c];
+    }
+
+    T smax[3] = {T(0), T(0), T(0)};
+    bool bad = false;
+    // invariant at the top: w0 = U_j, w1 = U_{j+1}, dprev = U_{j+1} - U_j,
+    // brp = Ub^R_j, fprev = F_{j-1/2}
+    for (int o = 0; o < len; ++o) {
+      const int j = j0 + o;
+      load_cell<T, LAY>(src, base + (face_index(j + 2, nd, mlo, mhi) + 2) * stride, G.ptot, w2);
+#pragma unroll
+      for (int c = 0; c < 5; ++c) dnext[c] = w2[c] - w1[c];
+      hancock<T, D>(w1, dprev, dnext, hl, bl, br);         // cell j + 1
+      T fcur[5], out[5];
+      hllc<T, D>(brp, bl, fcur);                           // face j + 1/2
+#pragma unroll
+      for (int c = 0; c < 5; ++c) out[c] = w0[c] - lam * (fcur[c] - fprev[c]);
+      if (active) store_cell<T, LAY>(dst, base + (int64_t)(j + 2) * stride, G.ptot, out);
+      if (p.fuse_s) {
+        T sc[3];
+        bool b_ = false;
+        wavespeeds(out, sc, b_);
+        if (active) {
+#pragma unroll
+          for (int d = 0; d < 3; ++d) smax[d] = __builtin_fmax(smax[d], sc[d]);
+          bad |= b_;
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < 5; ++c) {
+        fprev[c] = fcur[c];
+        brp[c] = br[c];
+        w0[c] = w1[c];
+        w1[c] = w2[c];
+        dprev[c] = dnext[c];
+      }
+    }
+    if (p.fuse_s) fold_wavespeeds<T>(smax, bad, p.w.s_acc + 3 * G.group, p.w.flag, red);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Wave speeds, time step, halo copies, fills
+// ---------------------------------------------------------------------------
+
+template <typename T, int LAY>
+__global__ void __launch_bounds__(WS_BLOCK) k_wavespeed(Work w, int in, TileRange tr,
+                                                        unsigned long long* s_out) {
+  __shared__ T red[3 * 16];
+  for (int64_t b = xcd_order(blockIdx.x, gridDim.x); b < tr.count; b += gridDim.x) {
+    const int64_t gt = tr.first + b;
+    const int g = find_grid(tr.tile_start, w.ngrids, gt);
+    const DevGrid& G = w.grids[g];
+    const int64_t lt = gt - tr.tile_start[g];
+    const uint32_t nx = G.n[0], ny = G.n[1];
+    const uint32_t ncell = nx * ny * (uint32_t)G.n[2];
+    T smax[3] = {T(0), T(0), T(0)};
+    bool bad = false;
+#pragma unroll
+    for (int m = 0; m < WS_CELLS_PER_THREAD; ++m) {
+      const int64_t f = lt * (WS_BLOCK * WS_CELLS_PER_THREAD) + m * WS_BLOCK + threadIdx.x;
+      if (f < ncell) {
+        const uint32_t fu = (uint32_t)f;
+        const uint32_t row = fu / nx;
+        const uint32_t i = fu - row * nx, jj = row % ny, kk = row / ny;
+        const int64_t q = (int64_t)(kk + 2) * G.pxy + (int64_t)(jj + 2) * G.px + (i + 2);
+        T u[5], s[3];
+        bool b_;
+        load_cell<T, LAY>(G.buf[in], q, G.ptot, u);
+        wavespeeds(u, s, b_);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) smax[d] = __builtin_fmax(smax[d], s[d]);
+        bad |= b_;
+      }
+    }
+    unsigned long long* slot = s_out ? s_out : w.s_acc + 3 * G.group;
+    fold_wavespeeds<T>(smax, bad, slot, w.flag, red);
+  }
+}
+
+// dt = cfl * min_d dx_d / S_d per grid from its group's maxima (or a fixed
+// dt), lam = dt / dx_d, time accumulated.  One workgroup; when reset_s is
+// set the maxima are cleared afterwards so the next z sweep can accumulate
+// the following step's values.
+__global__ void __launch_bounds__(256) k_dt(Work w, double cfl, double fixed_dt, int reset_s,
+                                            double* dt_out) {
+  for (int g = threadIdx.x; g < w.ngrids; g += blockDim.x) {
+    const DevGrid& G = w.grids[g];
+    double dt;
+    if (fixed_dt > 0.0) {
+      dt = fixed_dt;
+    } else {
+      const unsigned long long* s = w.s_acc + 3 * G.group;
+      double r = G.dx[0] / __longlong_as_double(s[0]);
+      for (int d = 1; d < 3; ++d) {
+        const double q = G.dx[d] / __longlong_as_double(s[d]);
+        if (q < r) r = q;
+      }
+      dt = cfl * r;
+      if (!(dt > 0.0) || !(dt < __builtin_huge_val())) {
+        *w.flag = 1u;
+        dt = 0.0;
+      }
+    }
+    for (int d = 0; d < 3; ++d) w.lam[g * 3 + d] = dt / G.dx[d];
+    w.t[g] += dt;
+    w.dt[g] = dt;
+    if (dt_out && g == 0) *dt_out = dt;
+  }
+  if (reset_s) {
+    __syncthreads();
+    for (int g = threadIdx.x; g < w.ngrids; g += blockDim.x)
+      for (int d = 0; d < 3; ++d) w.s_acc[g * 3 + d] = 0ull;
+  }
+}
+
+// Task = one linked face.  Two layers of the plane across `axis` (interior
+// extents, which match between the two sub-blocks) are copied from the
+// source's interior edge into the destination's padding.
+template <typename T, int LAY>
+__global__ void __launch_bounds__(256) k_halo(Work w, int buf, int axis, const HaloTask* tasks) {
+  const HaloTask tk = tasks[blockIdx.y];
+  const DevGrid& Gd = w.grids[tk.dst];
+  const DevGrid& Gs = w.grids[tk.src];
+  const int a0 = axis == 0 ? 1 : 0, a1 = axis == 2 ? 1 : 2;  // axes across
+  const uint32_t na = a0 == 0 ? Gd.n[0] : Gd.n[1];
+  const uint32_t nb = a1 == 1 ? Gd.n[1] : Gd.n[2];
+  const uint32_t area = na * nb;
+  const int64_t d_a0 = a0 == 1 ? Gd.px : 1, d_a1 = a1 == 1 ? Gd.px : Gd.pxy;
+  const int64_t s_a0 = a0 == 1 ? Gs.px : 1, s_a1 = a1 == 1 ? Gs.px : Gs.pxy;
+  const int64_t d_ax = axis == 0 ? 1 : (axis == 1 ? Gd.px : Gd.pxy);
+  const int64_t s_ax = axis == 0 ? 1 : (axis == 1 ? Gs.px : Gs.pxy);
+  const int nd = axis == 0 ? Gd.n[0] : (axis == 1 ? Gd.n[1] : Gd.n[2]);
+  const int ns = axis == 0 ? Gs.n[0] : (axis == 1 ? Gs.n[1] : Gs.n[2]);
+  for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < 2 * area;
+       e += gridDim.x * blockDim.x) {
+    const uint32_t layer = e / area, r = e - layer * area;
+    const uint32_t ia = r % na, ib = r / na;
+    // padded index along the axis: destination padding, source interior edge
+    const int dpos = tk.side == 0 ? (int)layer : nd + 2 + (int)layer;
+    const int spos = tk.side == 0 ? ns + (int)layer : 2 + (int)layer;
+    const int64_t across_d = (int64_t)(ia + 2) * d_a0 + (int64_t)(ib + 2) * d_a1;
+    const int64_t across_s = (int64_t)(ia + 2) * s_a0 + (int64_t)(ib + 2) * s_a1;
+    T u[5];
+    load_cell<T, LAY>(Gs.buf[buf], across_s + spos * s_ax, Gs.ptot, u);
+    store_cell<T, LAY>(Gd.buf[buf], across_d + dpos * d_ax, Gd.ptot, u);
+  }
+}
+
+__global__ void k_fill_u64(unsigned long long* p, int64_t n, unsigned long long v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void k_fill_f64(double* p, int64_t n, double v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Transfer and diagnostic kernels (runtime layout; not on the hot path)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int64_t desc_q(const Desc& d, int64_t f) {
+  const int64_t nx = d.n[0], ny = d.n[1];
+  const int64_t i = f % nx, row = f / nx, j = row % ny, k = row / ny;
+  return (k + 2) * d.pxy + (j + 2) * d.px + (i + 2);
+}
+
+__device__ __forceinline__ double load_rt(const Desc& d, int64_t q, int c) {
+  const int64_t o = offset_rt(d.lay, q, c, d.ptot);
+  return d.dtype == RIPPLE_FV_F32 ? (double)static_cast<const float*>(d.buf)[o]
+                                  : static_cast<const double*>(d.buf)[o];
+}
+
+__device__ __forceinline__ void store_rt(const Desc& d, int64_t q, int c, double v) {
+  const int64_t o = offset_rt(d.lay, q, c, d.ptot);
+  if (d.dtype == RIPPLE_FV_F32) static_cast<float*>(d.buf)[o] = (float)v;
+  else static_cast<double*>(d.buf)[o] = v;
+}
+
+// Primitive input: E = p / (gamma - 1) + rho |u|^2 / 2, computed in FP64.
+__global__ void k_import(Desc d, const double* src, int primitive) {
+  const int64_t ncell = (int64_t)d.n[0] * d.n[1] * d.n[2];
+  for (int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; f < ncell;
+       f += (int64_t)gridDim.x * blockDim.x) {
+    double v[5];
+    for (int c = 0; c < 5; ++c) v[c] = src[c * ncell + f];
+    if (primitive) {
+      const double rho = v[0], uu = v[1], vv = v[2], ww = v[3], pp = v[4];
+      v[1] = rho * uu;
+      v[2] = rho * vv;
+      v[3] = rho * ww;
+      v[4] = pp / (1.4 - 1.0) + 0.5 * rho * (uu * uu + vv * vv + ww * ww);
+    }
+    const int64_t q = desc_q(d, f);
+    for (int c = 0; c < 5; ++c) store_rt(d, q, c, v[c]);
+  }
+}
+
+__global__ void k_export(Desc d, double* dst) {
+  const int64_t ncell = (int64_t)d.n[0] * d.n[1] * d.n[2];
+  for (int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; f < ncell;
+       f += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t q = desc_q(d, f);
+    for (int c = 0; c < 5; ++c) dst[c * ncell + f] = load_rt(d, q, c);
+  }
+}
+
+__global__ void k_convert(Desc s, Desc d) {
+  const int64_t ncell = (int64_t)d.n[0] * d.n[1] * d.n[2];
+  for (int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; f < ncell;
+       f += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t qs = desc_q(s, f), qd = desc_q(d, f);
+    for (int c = 0; c < 5; ++c) store_rt(d, qd, c, load_rt(s, qs, c));
+  }
+}
+
+// Fixed-order tree reduction of NVAL doubles per thread over a block:
+// kind 0 = sum, 1 = max, chosen per value index.
+template <int NVAL>
+__device__ __forceinline__ void block_reduce(double v[NVAL], const int kind[NVAL], double* lds) {
+  const int tid = threadIdx.x;
+  for (int k = 0; k < NVAL; ++k) lds[k * DIAG_BLOCK + tid] = v[k];
+  __syncthreads();
+  for (int w = DIAG_BLOCK / 2; w > 0; w >>= 1) {
+    if (tid < w)
+      for (int k = 0; k < NVAL; ++k) {
+        const double a = lds[k * DIAG_BLOCK + tid], b = lds[k * DIAG_BLOCK + tid + w];
+        lds[k * DIAG_BLOCK + tid] = kind[k] ? __builtin_fmax(a, b) : a + b;
+      }
+    __syncthreads();
+  }
+  for (int k = 0; k < NVAL; ++k) v[k] = lds[k * DIAG_BLOCK];
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(DIAG_BLOCK) k_sums(Desc d, double* partials) {
+  __shared__ double lds[5 * DIAG_BLOCK];
+  const int kind[5] = {0, 0, 0, 0, 0};
+  const int64_t ncell = (int64_t)d.n[0] * d.n[1] * d.n[2];
+  double acc[5] = {0, 0, 0, 0, 0};
+  for (int64_t f = blockIdx.x * (int64_t)DIAG_BLOCK + threadIdx.x; f < ncell;
+       f += (int64_t)gridDim.x * DIAG_BLOCK) {
+    const int64_t q = desc_q(d, f);
+    for (int c = 0; c < 5; ++c) acc[c] += load_rt(d, q, c);
+  }
+  block_reduce<5>(acc, kind, lds);
+  if (threadIdx.x == 0)
+    for (int c = 0; c < 5; ++c) partials[blockIdx.x * 5 + c] = acc[c];
+}
+
+__global__ void __launch_bounds__(DIAG_BLOCK) k_norms(Desc d, const double* ref, double* partials) {
+  __shared__ double lds[20 * DIAG_BLOCK];
+  const int kind[20] = {0, 0, 1, 1, 0, 0, 1, 1, 0, 0, 1, 1, 0, 0, 1, 1, 0, 0, 1, 1};
+  const int64_t ncell = (int64_t)d.n[0] * d.n[1] * d.n[2];
+  double acc[20];
+  for (int k = 0; k < 20; ++k) acc[k] = 0.0;
+  for (int64_t f = blockIdx.x * (int64_t)DIAG_BLOCK + threadIdx.x; f < ncell;
+       f += (int64_t)gridDim.x * DIAG_BLOCK) {
+    const int64_t q = desc_q(d, f);
+    for (int c = 0; c < 5; ++c) {
+      const double a = load_rt(d, q, c), b = ref[c * ncell + f];
+      const double e = __builtin_fabs(a - b), m = __builtin_fabs(b);
+      acc[4 * c + 0] += e;
+      acc[4 * c + 1] += m;
+      acc[4 * c + 2] = __builtin_fmax(acc[4 * c + 2], e);
+      acc[4 * c + 3] = __builtin_fmax(acc[4 * c + 3], m);
+    }
+  }
+  block_reduce<20>(acc, kind, lds);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 20; ++k) partials[blockIdx.x * 20 + k] = acc[k];
+}
+
+template <int NVAL>
+__global__ void __launch_bounds__(DIAG_BLOCK) k_finish(const double* partials, int nblocks,
+                                                       double* out, int with_max) {
+  __shared__ double lds[NVAL * DIAG_BLOCK];
+  int kind[NVAL];
+  for (int k = 0; k < NVAL; ++k) kind[k] = with_max ? ((k & 3) >= 2) : 0;
+  double acc[NVAL];
+  for (int k = 0; k < NVAL; ++k) acc[k] = 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += DIAG_BLOCK)
+    for (int k = 0; k < NVAL; ++k) {
+      const double v = partials[b * NVAL + k];
+      acc[k] = kind[k] ? __builtin_fmax(acc[k], v) : acc[k] + v;
+    }
+  block_reduce<NVAL>(acc, kind, lds);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < NVAL; ++k) out[k] = acc[k];
+}
+
+// Smooth periodic primitive state used by the autotuner to time candidates
+// (rho = 1 + 0.2 sin, small velocities, p = 1), planar FP64 [5][n2][n1][n0].
+__global__ void k_tune_state(double* W, int nx, int ny, int nz) {
+  const int64_t ncell = (int64_t)nx * ny * nz;
+  const double two_pi = 6.283185307179586;
+  for (int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; f < ncell;
+       f += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = f % nx, row = f / nx, j = row % ny, k = row / ny;
+    const double x = (i + 0.5) / nx, y = (j + 0.5) / ny, z = (k + 0.5) / nz;
+    W[f] = 1.0 + 0.2 * sin(two_pi * (x + y + z));
+    W[ncell + f] = 0.1 * sin(two_pi * y);
+    W[2 * ncell + f] = 0.1 * sin(two_pi * z);
+    W[3 * ncell + f] = 0.1 * sin(two_pi * x);
+    W[4 * ncell + f] = 1.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host-side tile counts and launchers
+// ---------------------------------------------------------------------------
+
+int lay_of(const ripple_fv_grid& g) {
+  if (g.layout == RIPPLE_FV_AOS) return LAY_AOS;
+  if (g.layout == RIPPLE_FV_SOA) return LAY_SOA;
+  return g.aosoa_w == 16 ? LAY_AOSOA16 : (g.aosoa_w == 32 ? LAY_AOSOA32 : LAY_AOSOA64);
+}
+
+int64_t tiles_x(const ripple_fv_grid& g, int x_block) {
+  const int64_t total = (int64_t)(g.n[0] + 4) * g.n[1] * g.n[2];
+  const int64_t c = x_block - 4;
+  return (total + c - 1) / c;
+}
+
+int64_t tiles_yz(const ripple_fv_grid& g, int axis, int yz_block, int yz_segment) {
+  const int64_t nplane = (int64_t)g.n[0] * g.n[axis == 1 ? 2 : 1];
+  const int64_t nchunk = (nplane + yz_block - 1) / yz_block;
+  const int64_t nseg = (g.n[axis] + yz_segment - 1) / yz_segment;
+  return nchunk * nseg;
+}
+
+int64_t tiles_ws(const ripple_fv_grid& g) {
+  const int64_t ncell = (int64_t)g.n[0] * g.n[1] * g.n[2];
+  const int64_t per = WS_BLOCK * WS_CELLS_PER_THREAD;
+  return (ncell + per - 1) / per;
+}
+
+template <typename T, int LAY>
+static hipError_t sweep_typed(int axis, const Tiling& tl, const SweepParams& p, int blocks,
+                              hipStream_t s) {
+  if (axis == 0) {
+    if (tl.x_block == 128)
+      hipLaunchKernelGGL((k_sweep_x<T, LAY, 128>), dim3(blocks), dim3(128), 0, s, p);
+    else
+      hipLaunchKernelGGL((k_sweep_x<T, LAY, 256>), dim3(blocks), dim3(256), 0, s, p);
+  } else if (axis == 1) {
+    hipLaunchKernelGGL((k_sweep_yz<T, LAY, 1>), dim3(blocks), dim3(tl.yz_block), 0, s, p);
+  } else {
+    hipLaunchKernelGGL((k_sweep_yz<T, LAY, 2>), dim3(blocks), dim3(tl.yz_block), 0, s, p);
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t sweep_lay(int lay, int axis, const Tiling& tl, const SweepParams& p, int blocks,
+                            hipStream_t s) {
+  switch (lay) {
+    case LAY_AOS: return sweep_typed<T, LAY_AOS>(axis, tl, p, blocks, s);
+    case LAY_SOA: return sweep_typed<T, LAY_SOA>(axis, tl, p, blocks, s);
+    case LAY_AOSOA16: return sweep_typed<T, LAY_AOSOA16>(axis, tl, p, blocks, s);
+    case LAY_AOSOA32: return sweep_typed<T, LAY_AOSOA32>(axis, tl, p, blocks, s);
+    default: return sweep_typed<T, LAY_AOSOA64>(axis, tl, p, blocks, s);
+  }
+}
+
+hipError_t launch_sweep(int dtype, int lay, int axis, const Tiling& tl, const SweepParams& p,
+                        int grid_blocks, hipStream_t s) {
+  if (p.tiles.count <= 0) return hipSuccess;
+  return dtype == RIPPLE_FV_F32 ? sweep_lay<float>(lay, axis, tl, p, grid_blocks, s)
+                                : sweep_lay<double>(lay, axis, tl, p, grid_blocks, s);
+}
+
+template <typename T>
+static hipError_t ws_lay(int lay, const Work& w, int in, TileRange tr, unsigned long long* so,
+                         int blocks, hipStream_t s) {
+  switch (lay) {
+    case LAY_AOS: hipLaunchKernelGGL((k_wavespeed<T, LAY_AOS>), dim3(blocks), dim3(WS_BLOCK), 0, s, w, in, tr, so); break;
+    case LAY_SOA: hipLaunchKernelGGL((k_wavespeed<T, LAY_SOA>), dim3(blocks), dim3(WS_BLOCK), 0, s, w, in, tr, so); break;
+    case LAY_AOSOA16: hipLaunchKernelGGL((k_wavespeed<T, LAY_AOSOA16>), dim3(blocks), dim3(WS_BLOCK), 0, s, w, in, tr, so); break;
+    case LAY_AOSOA32: hipLaunchKernelGGL((k_wavespeed<T, LAY_AOSOA32>), dim3(blocks), dim3(WS_BLOCK), 0, s, w, in, tr, so); break;
+    default: hipLaunchKernelGGL((k_wavespeed<T, LAY_AOSOA64>), dim3(blocks), dim3(WS_BLOCK), 0, s, w, in, tr, so); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_wavespeed(int dtype, int lay, const Work& w, int in, TileRange tr,
+                            unsigned long long* s_out, int grid_blocks, hipStream_t s) {
+  if (tr.count <= 0) return hipSuccess;
+  return dtype == RIPPLE_FV_F32 ? ws_lay<float>(lay, w, in, tr, s_out, grid_blocks, s)
+                                : ws_lay<double>(lay, w, in, tr, s_out, grid_blocks, s);
+}
+
+hipError_t launch_dt(const Work& w, double cfl, double fixed_dt, int reset_s, double* dt_out,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_dt, dim3(1), dim3(256), 0, s, w, cfl, fixed_dt, reset_s, dt_out);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t halo_lay(int lay, const Work& w, int buf, int axis, const HaloTask* tasks,
+                           dim3 grid, hipStream_t s) {
+  switch (lay) {
+    case LAY_AOS: hipLaunchKernelGGL((k_halo<T, LAY_AOS>), grid, dim3(256), 0, s, w, buf, axis, tasks); break;
+    case LAY_SOA: hipLaunchKernelGGL((k_halo<T, LAY_SOA>), grid, dim3(256), 0, s, w, buf, axis, tasks); break;
+    case LAY_AOSOA16: hipLaunchKernelGGL((k_halo<T, LAY_AOSOA16>), grid, dim3(256), 0, s, w, buf, axis, tasks); break;
+    case LAY_AOSOA32: hipLaunchKernelGGL((k_halo<T, LAY_AOSOA32>), grid, dim3(256), 0, s, w, buf, axis, tasks); break;
+    default: hipLaunchKernelGGL((k_halo<T, LAY_AOSOA64>), grid, dim3(256), 0, s, w, buf, axis, tasks); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_halo(int dtype, int lay, const Work& w, int buf, int axis, const HaloTask* tasks,
+                       int ntasks, int64_t max_area, hipStream_t s) {
+  if (ntasks <= 0) return hipSuccess;
+  int64_t bx = (2 * max_area + 255) / 256;
+  if (bx > 4096) bx = 4096;
+  const dim3 grid((unsigned)bx, (unsigned)ntasks);
+  return dtype == RIPPLE_FV_F32 ? halo_lay<float>(lay, w, buf, axis, tasks, grid, s)
+                                : halo_lay<double>(lay, w, buf, axis, tasks, grid, s);
+}
+
+static unsigned fill_blocks(int64_t n) {
+  int64_t b = (n + 255) / 256;
+  return (unsigned)(b < 1 ? 1 : (b > 4096 ? 4096 : b));
+}
+
+hipError_t launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_u64, dim3(fill_blocks(n)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_f64, dim3(fill_blocks(n)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+static unsigned cell_blocks(const Desc& d) {
+  const int64_t ncell = (int64_t)d.n[0] * d.n[1] * d.n[2];
+  int64_t b = (ncell + 255) / 256;
+  return (unsigned)(b < 1 ? 1 : (b > 65536 ? 65536 : b));
+}
+
+hipError_t launch_import(const Desc& d, const double* src, int primitive, hipStream_t s) {
+  hipLaunchKernelGGL(k_import, dim3(cell_blocks(d)), dim3(256), 0, s, d, src, primitive);
+  return hipGetLastError();
+}
+
+hipError_t launch_export(const Desc& d, double* dst, hipStream_t s) {
+  hipLaunchKernelGGL(k_export, dim3(cell_blocks(d)), dim3(256), 0, s, d, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_convert(const Desc& src, const Desc& dst, hipStream_t s) {
+  hipLaunchKernelGGL(k_convert, dim3(cell_blocks(dst)), dim3(256), 0, s, src, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_tune_state(double* W, const int n[3], hipStream_t s) {
+  const int64_t ncell = (int64_t)n[0] * n[1] * n[2];
+  int64_t b = (ncell + 255) / 256;
+  b = b > 65536 ? 65536 : b;
+  hipLaunchKernelGGL(k_tune_state, dim3((unsigned)b), dim3(256), 0, s, W, n[0], n[1], n[2]);
+  return hipGetLastError();
+}
+
+hipError_t launch_sums(const Desc& d, double* partials, int nblocks, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_sums, dim3(nblocks), dim3(DIAG_BLOCK), 0, s, d, partials);
+  hipLaunchKernelGGL((k_finish<5>), dim3(1), dim3(DIAG_BLOCK), 0, s, partials, nblocks, out, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_norms(const Desc& d, const double* ref, double* partials, int nblocks,
+                        double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_norms, dim3(nblocks), dim3(DIAG_BLOCK), 0, s, d, ref, partials);
+  hipLaunchKernelGGL((k_finish<20>), dim3(1), dim3(DIAG_BLOCK), 0, s, partials, nblocks, out, 1);
+  return hipGetLastError();
+}
+
+}  // namespace rfv

@@ -158,18 +158,19 @@ def uniform(n, rho=1.0, u=0.0, v=0.0, w=0.0, p=1.0, device="cpu"):
     return W
 
 
-def random_physical(n, seed, device="cpu"):
-    """Cell-wise independent random states: rho, p in [0.5, 2), velocities in
-    [-1, 1).  For brute-force comparisons on tiny grids."""
+def random_physical(n, seed, device="cpu", spread=0.25, speed=0.3):
+    """Cell-wise independent random states for brute-force comparisons on
+    tiny grids: rho and p uniform in [1 - spread, 1 + spread), velocities
+    uniform in [-speed, speed)."""
     n = tuple(int(v_) for v_ in n)
     rng = SplitMix64(seed)
     count = n[0] * n[1] * n[2]
     vals = torch.tensor([rng.uniform() for _ in range(5 * count)], dtype=torch.float64)
     vals = vals.reshape(5, n[2], n[1], n[0])
     W = torch.empty_like(vals)
-    W[0] = 0.5 + 1.5 * vals[0]
-    W[1:4] = 2.0 * vals[1:4] - 1.0
-    W[4] = 0.5 + 1.5 * vals[4]
+    W[0] = 1.0 - spread + 2.0 * spread * vals[0]
+    W[1:4] = speed * (2.0 * vals[1:4] - 1.0)
+    W[4] = 1.0 - spread + 2.0 * spread * vals[4]
     return W.to(device)
 
 

@@ -1,0 +1,85 @@
+"""Helpers for the GPU tests: device buffers, import/export through the C ABI,
+and comparison against the FP64 oracle."""
+import numpy as np
+import torch
+
+from paper_2104_08571_amd import ripple_fv as R
+
+_CTX = None
+
+
+def ctx():
+    global _CTX
+    if _CTX is None:
+        _CTX = R.ripple_fv_create(0)
+    return _CTX
+
+
+def stream():
+    return torch.cuda.current_stream().cuda_stream
+
+
+def buffer(g, poison=True):
+    """A state buffer for grid g; NaN-filled so that reading padding that
+    nothing wrote shows up as NaN in the result."""
+    b = torch.empty(g.bytes, dtype=torch.uint8, device="cuda")
+    if poison:
+        (b.view(torch.float32) if g.dtype == R.F32 else b.view(torch.float64)).fill_(float("nan"))
+    return b
+
+
+def load(g, W, buf=None, variables=R.PRIMITIVE):
+    """Import an FP64 [5, nz, ny, nx] array (primitive by default) into a buffer."""
+    if buf is None:
+        buf = buffer(g)
+    src = torch.as_tensor(np.asarray(W) if not torch.is_tensor(W) else W,
+                          dtype=torch.float64).to("cuda").contiguous()
+    assert tuple(src.shape) == (5, g.n[2], g.n[1], g.n[0])
+    R.ripple_fv_import(ctx(), g, src.data_ptr(), variables, buf.data_ptr(), stream())
+    torch.cuda.synchronize()
+    return buf
+
+
+def export(g, buf):
+    dst = torch.empty((5, g.n[2], g.n[1], g.n[0]), dtype=torch.float64, device="cuda")
+    R.ripple_fv_export(ctx(), g, buf.data_ptr(), dst.data_ptr(), stream())
+    torch.cuda.synchronize()
+    return dst.cpu().numpy()
+
+
+def run(grids, states, nsteps, cfl=0.9, flags=R.RUN_EAGER):
+    """Run a batch from primitive initial states; returns (list of FP64
+    conserved arrays, list of times)."""
+    if isinstance(grids, R.Grid):
+        grids = [grids]
+        states = [states]
+    a = [load(g, W) for g, W in zip(grids, states)]
+    b = [buffer(g) for g in grids]
+    R.ripple_fv_run_batch(ctx(), grids, [x.data_ptr() for x in a], [x.data_ptr() for x in b],
+                          nsteps, cfl, flags, stream())
+    torch.cuda.synchronize()
+    assert R.ripple_fv_check(ctx()) == R.OK
+    t, _ = R.ripple_fv_batch_time(ctx(), grids)
+    res = b if nsteps % 2 == 1 else a
+    return [export(g, x) for g, x in zip(grids, res)], t
+
+
+def rel_l1(a, b):
+    """Per-variable relative L1 error sum|a - b| / sum|b| (0 when both vanish)."""
+    out = []
+    for c in range(5):
+        den = np.abs(b[c]).sum()
+        num = np.abs(a[c] - b[c]).sum()
+        out.append(num / den if den > 0 else (0.0 if num == 0 else np.inf))
+    return np.array(out)
+
+
+def assert_parity(gpu, ref, tol, what=""):
+    assert np.isfinite(gpu).all(), f"{what}: non-finite values in the GPU result"
+    err = rel_l1(gpu, ref)
+    assert (err <= tol).all(), f"{what}: relative L1 per variable {err} exceeds {tol}"
+    return err
+
+
+def unit_dx(n):
+    return [1.0 / n[0], 1.0 / n[1], 1.0 / n[2]]

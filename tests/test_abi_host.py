@@ -1,0 +1,94 @@
+"""The C-ABI library loads, exports every declared entry point, and its
+host-only logic (descriptor validation, partitioning) behaves as declared.
+No GPU needed: nothing here launches a kernel."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2104_08571_amd import ripple_fv as R
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    with open(os.path.join(ROOT, "include", "ripple_fv.h")) as f:
+        text = f.read()
+    decl = r"^(?:ripple_fv_status|void|const char\*)\s+(ripple_fv_[a-z_]+)\("
+    return sorted(set(re.findall(decl, text, flags=re.M)))
+
+
+def test_header_and_binding_agree():
+    assert declared_functions() == sorted(R.EXPORTED)
+
+
+def test_library_exports_every_symbol():
+    lib = R.lib()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_grid_struct_size():
+    # 3*4 + 3*4 + 3*8 + 4*4 + 6*4 + 4*4 + 3*8 + 8, no padding holes
+    assert ctypes.sizeof(R.Grid) == 136
+
+
+def test_grid_init_pitches():
+    g = R.make_grid((10, 7, 5), dtype=R.F32, layout=R.SOA)
+    assert list(g.pitch) == [14, 11, 9]
+    assert g.bytes == 14 * 11 * 9 * 5 * 4
+    g = R.make_grid((10, 7, 5), dtype=R.F64, layout=R.AOSOA, aosoa_w=16)
+    assert list(g.pitch) == [16, 11, 9]
+    assert g.bytes == 16 * 11 * 9 * 5 * 8
+    g = R.make_grid((60, 7, 5), dtype=R.F64, layout=R.AOSOA, aosoa_w=64)
+    assert g.pitch[0] == 64
+
+
+@pytest.mark.parametrize("bad", [
+    dict(n=(1, 4, 4)), dict(n=(4, 4, 0)), dict(dx=(0.0, 0.1, 0.1)), dict(dx=(-1.0, 0.1, 0.1)),
+    dict(dtype=2), dict(layout=3), dict(layout=R.AOSOA, aosoa_w=8), dict(layout=R.SOA, aosoa_w=16),
+    dict(bc=(0, 2, 0)), dict(tiling=(64, 0, 0, 0)), dict(tiling=(0, 512, 0, 0)),
+    dict(tiling=(0, 0, 2, 0)), dict(tiling=(0, 0, 0, -1)), dict(n=(2000, 2000, 2000)),
+])
+def test_grid_init_rejects(bad):
+    kw = dict(n=(8, 8, 8))
+    kw.update(bad)
+    with pytest.raises(R.RippleFVError) as e:
+        R.make_grid(**kw)
+    assert e.value.status == R.E_INVALID
+
+
+def test_status_strings():
+    assert R.ripple_fv_status_string(R.OK) == "ok"
+    assert R.ripple_fv_status_string(R.E_NONPHYSICAL) == "non-physical state"
+    assert R.ripple_fv_status_string(99) == "unknown status"
+
+
+def test_partition_links_and_extents():
+    whole = R.make_grid((10, 9, 8), dtype=R.F32, bc=(R.TRANSMISSIVE, R.PERIODIC, R.TRANSMISSIVE))
+    subs = R.ripple_fv_partition(whole, (2, 3, 1), first_index=4)
+    assert len(subs) == 6
+    # extents split as evenly as possible; x fastest
+    assert [list(s.n) for s in subs] == [[5, 3, 8], [5, 3, 8]] * 3
+    for idx, s in enumerate(subs):
+        a, b = idx % 2, idx // 2
+        assert s.group == 4
+        assert list(s.dx) == list(whole.dx)
+        # x: transmissive, two parts -> inner faces linked only
+        assert s.nbr[0] == (-1 if a == 0 else 4 + idx - 1)
+        assert s.nbr[1] == (-1 if a == 1 else 4 + idx + 1)
+        # y: periodic, three parts -> linked around
+        assert s.nbr[2] == 4 + a + 2 * ((b - 1) % 3)
+        assert s.nbr[3] == 4 + a + 2 * ((b + 1) % 3)
+        # z: one part, transmissive -> physical
+        assert s.nbr[4] == -1 and s.nbr[5] == -1
+        assert s.bytes == s.pitch[0] * s.pitch[1] * s.pitch[2] * 5 * 4
+    odd = R.ripple_fv_partition(R.make_grid((11, 4, 4)), (2, 1, 1))
+    assert [o.n[0] for o in odd] == [6, 5]
+
+
+def test_partition_rejects_too_thin():
+    whole = R.make_grid((6, 6, 6))
+    with pytest.raises(R.RippleFVError):
+        R.ripple_fv_partition(whole, (4, 1, 1))

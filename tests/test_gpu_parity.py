@@ -1,0 +1,163 @@
+"""HIP path against the FP64 oracle, through the C ABI.
+
+Tolerances: FP64 relative L1 per conserved variable <= 1e-12, FP32 <= 1e-5
+(the bars the method's precision targets set).  Grids span several tiles of
+every kernel and have ragged tails (extents that are not multiples of the
+tile sizes).  Padding is NaN-poisoned before the initial state is loaded, so
+a kernel that reads padding nothing wrote produces NaN and fails the test.
+"""
+import numpy as np
+import pytest
+import torch
+
+import gpu_util as G
+from paper_2104_08571_amd import initial_states as ist
+from paper_2104_08571_amd import ripple_fv as R
+
+pytestmark = pytest.mark.gpu
+
+TOL = {R.F64: 1e-12, R.F32: 1e-5}
+LAYOUTS = [(R.SOA, 0), (R.AOS, 0), (R.AOSOA, 16), (R.AOSOA, 32), (R.AOSOA, 64)]
+LAYOUT_IDS = ["soa", "aos", "aosoa16", "aosoa32", "aosoa64"]
+
+
+@pytest.mark.parametrize("dtype", [R.F64, R.F32], ids=["f64", "f32"])
+@pytest.mark.parametrize("layout", LAYOUTS, ids=LAYOUT_IDS)
+@pytest.mark.parametrize("shape", [(2, 3, 5), (7, 5, 3), (37, 29, 23)])
+@pytest.mark.parametrize("bc", [0, 1], ids=["transmissive", "periodic"])
+def test_single_sweep(oracle, dtype, layout, shape, bc):
+    """One sweep along each axis with the oracle's dt, on random cell states."""
+    W = ist.random_physical(shape, seed=sum(shape) + bc).numpy()
+    U0 = oracle.prim_to_cons(W)
+    dx = G.unit_dx(shape)
+    dt = oracle.dt(oracle.max_wavespeed(U0), dx, 0.9)
+    g = R.make_grid(shape, dtype=dtype, layout=layout[0], aosoa_w=layout[1], bc=(bc,) * 3)
+    src = G.load(g, W)
+    for axis in range(3):
+        dst = G.buffer(g)
+        R.ripple_fv_sweep(G.ctx(), g, axis, src.data_ptr(), dst.data_ptr(), dt, G.stream())
+        gpu = G.export(g, dst)
+        ref = oracle.sweep(U0, axis, dt, dx, [bc] * 3)
+        G.assert_parity(gpu, ref, TOL[dtype], f"axis {axis}")
+
+
+def test_sod_32_fp64_aos(oracle):
+    """Sod along x, 32^3, FP64, AoS, transmissive, CFL 0.9, 20 steps."""
+    W = ist.sod((32, 32, 32))
+    g = R.make_grid((32, 32, 32), dtype=R.F64, layout=R.AOS)
+    (gpu,), (t,) = G.run(g, W, 20)
+    ref, t_ref, _ = oracle.run(oracle.prim_to_cons(W.numpy()), 20, G.unit_dx((32,) * 3), [0, 0, 0])
+    err = G.assert_parity(gpu, ref, 1e-12, "sod 32^3")
+    assert abs(t - t_ref) <= 1e-12 * t_ref
+    # planar: the transverse momenta stay exactly zero
+    assert not gpu[2].any() and not gpu[3].any()
+    print("sod32 rel L1", err)
+
+
+@pytest.mark.parametrize("layout", LAYOUTS[:3], ids=LAYOUT_IDS[:3])
+def test_smooth_periodic_fp64(oracle, layout):
+    shape = (48, 40, 36)
+    W = ist.smooth_periodic(shape, seed=2104)
+    g = R.make_grid(shape, dtype=R.F64, layout=layout[0], aosoa_w=layout[1], bc=(1, 1, 1))
+    (gpu,), (t,) = G.run(g, W, 12)
+    ref, t_ref, _ = oracle.run(oracle.prim_to_cons(W.numpy()), 12, G.unit_dx(shape), [1, 1, 1])
+    G.assert_parity(gpu, ref, 1e-12)
+    assert abs(t - t_ref) <= 1e-12 * t_ref
+
+
+def test_smooth_periodic_fp32(oracle):
+    shape = (48, 40, 36)
+    W = ist.smooth_periodic(shape, seed=8571)
+    g = R.make_grid(shape, dtype=R.F32, layout=R.SOA, bc=(1, 1, 1))
+    (gpu,), (t,) = G.run(g, W, 20)
+    ref, t_ref, _ = oracle.run(oracle.prim_to_cons(W.numpy()), 20, G.unit_dx(shape), [1, 1, 1])
+    err = G.assert_parity(gpu, ref, 1e-5)
+    assert abs(t - t_ref) <= 1e-5 * t_ref
+    print("fp32 rel L1", err)
+
+
+def test_mixed_boundaries_anisotropic(oracle):
+    """Different extents, cell widths and boundary conditions per axis."""
+    shape = (29, 21, 17)
+    W = ist.random_physical(shape, seed=99)
+    dx = (0.7 / 29, 1.3 / 21, 1.0 / 17)
+    g = R.make_grid(shape, dtype=R.F64, layout=R.SOA, bc=(1, 0, 1), dx=dx)
+    (gpu,), (t,) = G.run(g, W, 5)
+    ref, t_ref, _ = oracle.run(oracle.prim_to_cons(W.numpy()), 5, dx, [1, 0, 1])
+    G.assert_parity(gpu, ref, 1e-12)
+
+
+@pytest.mark.parametrize("dtype", [R.F64, R.F32], ids=["f64", "f32"])
+@pytest.mark.parametrize("bc", [0, 1])
+def test_uniform_state_bitwise(dtype, bc):
+    shape = (19, 13, 11)
+    W = ist.uniform(shape, rho=1.3, u=0.4, v=-0.2, w=0.7, p=2.1)
+    g = R.make_grid(shape, dtype=dtype, layout=R.AOS, bc=(bc,) * 3)
+    U0 = G.export(g, G.load(g, W))
+    (gpu,), _ = G.run(g, W, 3)
+    assert np.array_equal(gpu, U0)
+
+
+def test_max_wavespeed(oracle):
+    shape = (33, 17, 9)
+    W = ist.smooth_periodic(shape, seed=3)
+    U = oracle.prim_to_cons(W.numpy())
+    for dtype in (R.F64, R.F32):
+        g = R.make_grid(shape, dtype=dtype, layout=R.SOA)
+        buf = G.load(g, W)
+        s = torch.zeros(3, dtype=torch.float64, device="cuda")
+        R.ripple_fv_max_wavespeed(G.ctx(), g, buf.data_ptr(), s.data_ptr(), G.stream())
+        torch.cuda.synchronize()
+        np.testing.assert_allclose(s.cpu().numpy(), oracle.max_wavespeed(U),
+                                   rtol=1e-15 if dtype == R.F64 else 1e-6)
+
+
+def test_conserved_sums_and_norms():
+    shape = (21, 19, 17)
+    W = ist.smooth_periodic(shape, seed=5)
+    g = R.make_grid(shape, dtype=R.F64, layout=R.AOSOA, aosoa_w=32)
+    buf = G.load(g, W)
+    U = G.export(g, buf)
+    sums = torch.zeros(5, dtype=torch.float64, device="cuda")
+    R.ripple_fv_conserved_sums(G.ctx(), g, buf.data_ptr(), sums.data_ptr(), G.stream())
+    ref = torch.as_tensor(U + 0.01 * np.sin(np.arange(U.size)).reshape(U.shape)).cuda()
+    out = torch.zeros(20, dtype=torch.float64, device="cuda")
+    R.ripple_fv_error_norms(G.ctx(), g, buf.data_ptr(), ref.data_ptr(), out.data_ptr(), G.stream())
+    torch.cuda.synchronize()
+    # totals can cancel to ~0 (zero-mean momenta): compare against the sum of |U|
+    scale = np.abs(U).reshape(5, -1).sum(1)
+    assert (np.abs(sums.cpu().numpy() - U.reshape(5, -1).sum(1)) <= 1e-13 * scale).all()
+    o = out.cpu().numpy().reshape(5, 4)
+    r = ref.cpu().numpy()
+    for c in range(5):
+        np.testing.assert_allclose(o[c, 0], np.abs(U[c] - r[c]).sum(), rtol=1e-12)
+        np.testing.assert_allclose(o[c, 1], np.abs(r[c]).sum(), rtol=1e-12)
+        assert o[c, 2] == np.abs(U[c] - r[c]).max()
+        assert o[c, 3] == np.abs(r[c]).max()
+
+
+def test_import_export_roundtrip_and_convert():
+    shape = (13, 7, 5)
+    W = ist.random_physical(shape, seed=1)
+    base = R.make_grid(shape, dtype=R.F64, layout=R.SOA)
+    U = G.export(base, G.load(base, W))
+    for lay, w in LAYOUTS:
+        g = R.make_grid(shape, dtype=R.F64, layout=lay, aosoa_w=w)
+        buf = G.load(g, U, variables=R.CONSERVED)
+        assert np.array_equal(G.export(g, buf), U)
+        g32 = R.make_grid(shape, dtype=R.F32, layout=R.AOS)
+        b32 = G.buffer(g32)
+        R.ripple_fv_convert(G.ctx(), g, buf.data_ptr(), g32, b32.data_ptr(), G.stream())
+        got = G.export(g32, b32)
+        assert np.array_equal(got, U.astype(np.float32).astype(np.float64))
+
+
+def test_nonphysical_flag_and_recovery():
+    shape = (9, 8, 7)
+    W = ist.uniform(shape)
+    W[4, 3, 2, 1] = -0.5
+    g = R.make_grid(shape, dtype=R.F64, layout=R.SOA)
+    a, b = G.load(g, W), G.buffer(g)
+    R.ripple_fv_run_batch(G.ctx(), [g], [a.data_ptr()], [b.data_ptr()], 1, 0.9, 0, G.stream())
+    assert R.ripple_fv_check(G.ctx()) == R.E_NONPHYSICAL
+    assert R.ripple_fv_check(G.ctx()) == R.OK  # cleared by the first check
