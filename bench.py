@@ -91,6 +91,91 @@ def run_gpu(n, dtype, layout, aosoa_w, steps, warmup, seed, tiling):
     return {"seconds": t1 - t0, "graph_seconds": t3 - t2, "profile": prof, "status": status}
 
 
+def run_batch_workload(steps, warmup):
+    """64 grids with extents drawn from {32, 48, ..., 192} (FP32, periodic):
+    layout and tiling chosen by the autotuner, then batched persistent
+    launches replayed as hipGraphs vs one launch per grid per kernel."""
+    import torch
+
+    from paper_2104_08571_amd import initial_states as ist
+    from paper_2104_08571_amd import ripple_fv as R
+
+    ctx = R.ripple_fv_create(0)
+    stream = torch.cuda.current_stream().cuda_stream
+    ext = ist.batch_extents(64, seed=42)
+    base = [R.make_grid(e, dtype=R.F32, layout=R.SOA, bc=(R.PERIODIC,) * 3) for e in ext]
+    t0 = time.perf_counter()
+    grids = R.ripple_fv_batch_tune(ctx, base, stream)
+    tune_s = time.perf_counter() - t0
+    a, b = [], []
+    for i, (g, e) in enumerate(zip(grids, ext)):
+        W = ist.smooth_periodic(e, seed=1000 + i, device="cuda")
+        a.append(torch.empty(g.bytes, dtype=torch.uint8, device="cuda"))
+        b.append(torch.empty(g.bytes, dtype=torch.uint8, device="cuda"))
+        R.ripple_fv_import(ctx, g, W.data_ptr(), R.PRIMITIVE, a[-1].data_ptr(), stream)
+    pa, pb = [x.data_ptr() for x in a], [x.data_ptr() for x in b]
+    cells = sum(e[0] * e[1] * e[2] for e in ext)
+    out = {"grids": 64, "cells": cells, "tune_seconds": round(tune_s, 2),
+           "chosen": {"layout": ["aos", "soa", "aosoa"][grids[0].layout], "aosoa_w": grids[0].aosoa_w,
+                      "x_block": grids[0].x_block, "yz_block": grids[0].yz_block,
+                      "yz_segment": grids[0].yz_segment, "persist": grids[0].persist}}
+    for name, flags in (("batched_graph", R.RUN_GRAPH), ("batched_eager", R.RUN_EAGER),
+                        ("per_grid", R.RUN_PER_GRID)):
+        R.ripple_fv_run_batch(ctx, grids, pa, pb, warmup, 0.9, flags, stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        R.ripple_fv_run_batch(ctx, grids, pa, pb, steps, 0.9, flags, stream)
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        out[name] = {"gcell_updates_per_s": round(cells * steps / secs / 1e9, 3),
+                     "ms_per_step": round(secs / steps * 1e3, 4)}
+    out["status"] = R.ripple_fv_check(ctx)
+    R.ripple_fv_destroy(ctx)
+    return out
+
+
+def run_partition_workload(steps, warmup):
+    """768^3 FP32 blast wave as 2 x 2 x 2 sub-blocks of 384^3 with on-device
+    halo copies each sweep (one GPU's share of a partitioned run)."""
+    import torch
+
+    from paper_2104_08571_amd import initial_states as ist
+    from paper_2104_08571_amd import ripple_fv as R
+
+    ctx = R.ripple_fv_create(0)
+    stream = torch.cuda.current_stream().cuda_stream
+    n = (768, 768, 768)
+    whole = R.make_grid(n, dtype=R.F32, layout=R.SOA)
+    subs = R.ripple_fv_partition(whole, (2, 2, 2))
+    a, b = [], []
+    for i, s in enumerate(subs):
+        o = ((i % 2) * 384, ((i // 2) % 2) * 384, (i // 4) * 384)
+        W = ist.blast((384, 384, 384), origin=o, n_global=n, device="cuda")
+        a.append(torch.empty(s.bytes, dtype=torch.uint8, device="cuda"))
+        b.append(torch.empty(s.bytes, dtype=torch.uint8, device="cuda"))
+        R.ripple_fv_import(ctx, s, W.data_ptr(), R.PRIMITIVE, a[-1].data_ptr(), stream)
+        del W
+    pa, pb = [x.data_ptr() for x in a], [x.data_ptr() for x in b]
+    R.ripple_fv_run_batch(ctx, subs, pa, pb, warmup, 0.9, R.RUN_EAGER, stream)
+    torch.cuda.synchronize()
+    R.ripple_fv_profile(ctx)
+    t0 = time.perf_counter()
+    R.ripple_fv_run_batch(ctx, subs, pa, pb, steps, 0.9, R.RUN_PROFILE, stream)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    prof = R.ripple_fv_profile(ctx)
+    cells = 768 ** 3
+    out = {"cells": cells, "sub_blocks": 8, "gcell_updates_per_s": round(cells * steps / secs / 1e9, 3),
+           "ms_per_step": round(secs / steps * 1e3, 4),
+           "kernel_ms": {k: (round(ms / c, 4) if c else None) for k, (ms, c) in prof.items()},
+           "halo_ms_per_step": round(prof["halo"][0] / steps, 4),
+           "status": R.ripple_fv_check(ctx)}
+    R.ripple_fv_destroy(ctx)
+    del a, b
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(n, seed, steps):
     import numpy as np  # noqa: F401
 
@@ -123,6 +208,8 @@ def main():
     ap.add_argument("--no-f64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--cpu-steps", type=int, default=1,
                     help="oracle steps timed for cpu_baseline (0 = skip)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the batched and partitioned workloads")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -167,6 +254,13 @@ def main():
               f"{f64['ms_per_step']:.3f} ms/step, kernels {f64['kernel_ms']}", file=sys.stderr,
               flush=True)
 
+    batch = part = None
+    if not args.no_extra:
+        batch = run_batch_workload(args.steps, args.warmup)
+        print(f"[bench] batch 64 grids: {batch}", file=sys.stderr, flush=True)
+        part = run_partition_workload(args.steps, args.warmup)
+        print(f"[bench] partition 768^3: {part}", file=sys.stderr, flush=True)
+
     base = None
     if args.cpu_steps > 0:
         base = cpu_baseline(n, seed, args.cpu_steps)
@@ -208,6 +302,10 @@ def main():
                       "kernel_ms": f64["kernel_ms"],
                       "dominant": f64["dominant"],
                       "dominant_achieved_GBps": round(f64["dominant_achieved_GBps"], 1)}
+    if batch is not None:
+        out["batch_64_grids_f32"] = batch
+    if part is not None:
+        out["partition_768_f32_2x2x2"] = part
     print(json.dumps(out), flush=True)
 
 

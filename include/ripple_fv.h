@@ -20,7 +20,7 @@
  * and its polymorphic data layout (section "Polymorphic Data Layout": the
  * same cell type stored contiguously or strided), extended by a blocked
  * layout.  With padded cell indices (i, j, k) -- interior cell (0, 0, 0) at
- * (2, 2, 2) -- pitches Px, Py, Pz and q = (k Py + j) Px + i:
+ * (2, 2, 2) -- pitches Px (even), Py, Pz and q = (k Py + j) Px + i:
  *
  *   RIPPLE_FV_AOS    element (q, c) at  q * 5 + c            (contiguous)
  *   RIPPLE_FV_SOA    element (q, c) at  c * Px Py Pz + q     (strided)
@@ -101,8 +101,15 @@ enum ripple_fv_kernel_kind {
  *  nbr      sub-block links per face (-x, +x, -y, +y, -z, +z): batch index of
  *           the neighbouring sub-block whose interior fills this face's
  *           padding, or -1 when the face is a physical boundary
- *  x_block, yz_block, yz_segment, persist   kernel tiling chosen by
- *           ripple_fv_batch_tune (0 = defaults); they never change results
+ *  x_block, yz_block, yz_segment, persist, yz_cols   kernel tiling chosen by
+ *           ripple_fv_batch_tune (0 = defaults); they never change results.
+ *           x_block: threads per workgroup of the x sweep (128, 256);
+ *           yz_block: threads per workgroup of the y/z sweeps (64, 128, 256);
+ *           yz_segment: cells each y/z thread advances (>= 4);
+ *           persist: workgroups per CU of persistent launches (0 = one per tile);
+ *           yz_cols: adjacent x cells per y/z thread (1, 2; 0 = 2 for FP32
+ *           SoA/AoSoA, else 1)
+ *  reserved must be 0
  *  pitch, bytes   OUT: padded extents (Px, Py, Pz) and bytes of one buffer */
 typedef struct ripple_fv_grid {
   int32_t n[3];
@@ -117,6 +124,8 @@ typedef struct ripple_fv_grid {
   int32_t yz_block;
   int32_t yz_segment;
   int32_t persist;
+  int32_t yz_cols;
+  int32_t reserved;
   int64_t pitch[3];
   int64_t bytes;
 } ripple_fv_grid;
@@ -124,8 +133,8 @@ typedef struct ripple_fv_grid {
 typedef struct ripple_fv_ctx ripple_fv_ctx;
 
 /* Validate a descriptor and fill pitch[] and bytes.  Px = n[0] + 4 rounded
- * up to a multiple of aosoa_w for AOSOA; Py = n[1] + 4; Pz = n[2] + 4
- * (section "Tensors": padding is part of the tensor's storage).
+ * up to an even number (to a multiple of aosoa_w for AOSOA); Py = n[1] + 4;
+ * Pz = n[2] + 4 (section "Tensors": padding is part of the tensor's storage).
  * E_INVALID on extents < 2, dx <= 0, unknown enums, bad aosoa_w, bad tiling
  * knobs, or a buffer size above 2^46 bytes. */
 ripple_fv_status ripple_fv_grid_init(ripple_fv_grid* g);

@@ -2,9 +2,11 @@
 
 Each translation unit is compiled by hipcc to an object, in parallel, and the
 objects are linked into paper_2104_08571_amd/libripple_fv.so.  Flags:
-  -ffp-contract=off   no implicit fused multiply-add: every kernel variant
-                      performs the same operations on a cell (bitwise
-                      invariance across layouts, tilings and batching)
+  -ffp-contract=off   no implicit fused multiply-add: FMAs appear only where
+                      the device code writes them, so every inlined copy of
+                      the cell arithmetic rounds identically (bitwise
+                      invariance across layouts, tilings, batching and
+                      partitioning)
   -packed-fp32-ops    disabled target feature: no packed FP32 instructions
 """
 import os

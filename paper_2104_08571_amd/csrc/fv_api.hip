@@ -132,11 +132,12 @@ ripple_fv_status grid_check(const ripple_fv_grid* g, int64_t pitch[3], int64_t* 
   }
   if (!valid_block(g->x_block, {0, 128, 256}) || !valid_block(g->yz_block, {0, 64, 128, 256}) ||
       g->yz_segment < 0 || (g->yz_segment > 0 && g->yz_segment < 4) || g->yz_segment > 4096 ||
-      g->persist < 0 || g->persist > 64) {
+      g->persist < 0 || g->persist > 64 || !valid_block(g->yz_cols, {0, 1, 2}) || g->reserved != 0) {
     *why = "bad tiling knobs";
     return RIPPLE_FV_E_INVALID;
   }
-  int64_t px = g->n[0] + 4;
+  // even row pitch: pairs of x cells start on 8-byte (FP32) / 16-byte (FP64) boundaries
+  int64_t px = (g->n[0] + 4 + 1) / 2 * 2;
   if (g->layout == RIPPLE_FV_AOSOA) px = (px + g->aosoa_w - 1) / g->aosoa_w * g->aosoa_w;
   const int64_t py = g->n[1] + 4, pz = g->n[2] + 4;
   const int64_t cells = px * py * pz;
@@ -161,6 +162,10 @@ Tiling tiling_of(const ripple_fv_grid& g) {
   t.yz_block = g.yz_block ? g.yz_block : 256;
   t.yz_segment = g.yz_segment ? g.yz_segment : 64;
   t.persist = g.persist;
+  // two x cells per y/z thread pays off where it widens the accesses (FP32
+  // SoA/AoSoA); FP64 already moves 8 bytes per lane and would lose occupancy
+  t.yz_cols = g.yz_cols ? g.yz_cols
+                        : ((g.layout != RIPPLE_FV_AOS && g.dtype == RIPPLE_FV_F32) ? 2 : 1);
   return t;
 }
 
@@ -229,7 +234,7 @@ ripple_fv_status validate_batch(ripple_fv_ctx* ctx, int n, const ripple_fv_grid*
     if (G.dtype != g0.dtype || G.layout != g0.layout || G.aosoa_w != g0.aosoa_w)
       return fail(ctx, RIPPLE_FV_E_UNSUPPORTED, "grids of a batch must share layout and dtype");
     if (G.x_block != g0.x_block || G.yz_block != g0.yz_block || G.yz_segment != g0.yz_segment ||
-        G.persist != g0.persist)
+        G.persist != g0.persist || G.yz_cols != g0.yz_cols)
       return fail(ctx, RIPPLE_FV_E_UNSUPPORTED, "grids of a batch must share tiling knobs");
   }
   for (int g = 0; g < n; ++g) {
@@ -277,8 +282,10 @@ ripple_fv_status build_plan(ripple_fv_ctx* ctx, int n, const ripple_fv_grid* gri
   for (int k = 0; k < 4; ++k) P->tiles[k].assign(n + 1, 0);
   for (int g = 0; g < n; ++g) {
     P->tiles[0][g + 1] = P->tiles[0][g] + tiles_x(grids[g], P->tl.x_block);
-    P->tiles[1][g + 1] = P->tiles[1][g] + tiles_yz(grids[g], 1, P->tl.yz_block, P->tl.yz_segment);
-    P->tiles[2][g + 1] = P->tiles[2][g] + tiles_yz(grids[g], 2, P->tl.yz_block, P->tl.yz_segment);
+    P->tiles[1][g + 1] = P->tiles[1][g] + tiles_yz(grids[g], 1, P->tl.yz_block, P->tl.yz_segment,
+                                                   P->tl.yz_cols);
+    P->tiles[2][g + 1] = P->tiles[2][g] + tiles_yz(grids[g], 2, P->tl.yz_block, P->tl.yz_segment,
+                                                   P->tl.yz_cols);
     P->tiles[3][g + 1] = P->tiles[3][g] + tiles_ws(grids[g]);
   }
   for (int axis = 0; axis < 3; ++axis) {
@@ -986,7 +993,7 @@ extern "C" ripple_fv_status ripple_fv_batch_tune(ripple_fv_ctx* ctx, int32_t n,
   for (auto& g : base) {
     g.layout = RIPPLE_FV_SOA;
     g.aosoa_w = 0;
-    g.x_block = g.yz_block = g.yz_segment = g.persist = 0;
+    g.x_block = g.yz_block = g.yz_segment = g.persist = g.yz_cols = 0;
     if (ripple_fv_grid_init(&g)) return fail(ctx, RIPPLE_FV_E_INVALID, "bad grid descriptor");
   }
   if ((st = validate_batch(ctx, n, base.data()))) return st;
@@ -1041,7 +1048,12 @@ extern "C" ripple_fv_status ripple_fv_batch_tune(ripple_fv_ctx* ctx, int32_t n,
       if (st) break;
       st = consider(with([&](ripple_fv_grid& g) { g.yz_block = yb; g.yz_segment = sg; }));
     }
-  // 4. persistent launches
+  // 4. x cells per y/z thread
+  for (int cols : {1, 2}) {
+    if (st) break;
+    st = consider(with([&](ripple_fv_grid& g) { g.yz_cols = cols; }));
+  }
+  // 5. persistent launches
   for (int pc : {0, 2, 4, 8}) {
     if (st) break;
     st = consider(with([&](ripple_fv_grid& g) { g.persist = pc; }));

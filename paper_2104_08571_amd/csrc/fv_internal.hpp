@@ -72,13 +72,14 @@ struct Tiling {
   int yz_block;    // lanes per workgroup of the y/z sweeps (64, 128, 256)
   int yz_segment;  // cells per thread along y/z
   int persist;     // workgroups per CU for persistent launches, 0 = one per tile
+  int yz_cols;     // adjacent x cells per thread in the y/z sweeps (1 or 2)
 };
 
 int lay_of(const ripple_fv_grid& g);
 
 // Tile counts of one grid (must match the kernels' decoding).
 int64_t tiles_x(const ripple_fv_grid& g, int x_block);
-int64_t tiles_yz(const ripple_fv_grid& g, int axis, int yz_block, int yz_segment);
+int64_t tiles_yz(const ripple_fv_grid& g, int axis, int yz_block, int yz_segment, int yz_cols);
 int64_t tiles_ws(const ripple_fv_grid& g);
 constexpr int WS_BLOCK = 256;
 constexpr int WS_CELLS_PER_THREAD = 4;

@@ -47,7 +47,7 @@ __device__ __forceinline__ int find_grid(const int64_t* start, int n, int64_t t)
     const int mid = (lo + hi + 1) >> 1;
     if (start[mid] <= t) lo = mid; else hi = mid - 1;
   }
-  return lo;
+  return uniform(lo);
 }
 
 // Interior index to load for position j (may lie in [-2, n+1]) along an axis:
@@ -58,10 +58,20 @@ __device__ __forceinline__ int face_index(int j, int n, int mode_lo, int mode_hi
   return j;
 }
 
+// Maximum of two non-negative values by their bit patterns (they order like
+// unsigned integers); a NaN pattern exceeds every finite one, so it wins.
+__device__ __forceinline__ float bits_max(float a, float b) {
+  return __builtin_bit_cast(float, max(__builtin_bit_cast(uint32_t, a), __builtin_bit_cast(uint32_t, b)));
+}
+__device__ __forceinline__ double bits_max(double a, double b) {
+  const uint64_t x = __builtin_bit_cast(uint64_t, a), y = __builtin_bit_cast(uint64_t, b);
+  return __builtin_bit_cast(double, x > y ? x : y);
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_max(T v) {
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = __builtin_fmax(v, __shfl_xor(v, o, 64));
+  for (int o = 32; o > 0; o >>= 1) v = bits_max(v, __shfl_xor(v, o, 64));
   return v;
 }
 
@@ -82,7 +92,7 @@ __device__ __forceinline__ void fold_wavespeeds(T s[3], bool bad, unsigned long 
   __syncthreads();
   if (threadIdx.x < 3) {
     T m = lds[threadIdx.x];
-    for (int wv = 1; wv < nwave; ++wv) m = __builtin_fmax(m, lds[wv * 3 + threadIdx.x]);
+    for (int wv = 1; wv < nwave; ++wv) m = bits_max(m, lds[wv * 3 + threadIdx.x]);
     const unsigned long long bits = __double_as_longlong((double)m);
     if (bits > __atomic_load_n(&slot[threadIdx.x], __ATOMIC_RELAXED))
       atomicMax(&slot[threadIdx.x], bits);
@@ -100,16 +110,18 @@ __device__ __forceinline__ void fold_wavespeeds(T s[3], bool bad, unsigned long 
 // P0 - 2 + t; threads 2 .. NT-3 write the interior cells among them, so each
 // chunk produces up to NT - 4 cells and overlaps its neighbours by 4.
 template <typename T, int LAY, int NT>
-__global__ void __launch_bounds__(NT) k_sweep_x(SweepParams p) {
+__global__ void __launch_bounds__(NT) k_sweep_x(SweepParams p, const DevGrid* __restrict__ grids,
+                                                const int64_t* __restrict__ tile_start,
+                                                const double* __restrict__ lamv) {
   constexpr int C = NT - 4;
   __shared__ T sA[5][NT];
   __shared__ T sB[5][NT];
   const int tid = threadIdx.x;
   for (int64_t b = xcd_order(blockIdx.x, gridDim.x); b < p.tiles.count; b += gridDim.x) {
-    const int64_t gt = p.tiles.first + b;
-    const int g = find_grid(p.tiles.tile_start, p.w.ngrids, gt);
-    const DevGrid& G = p.w.grids[g];
-    const int64_t lt = gt - p.tiles.tile_start[g];
+    const int64_t gt = uniform(p.tiles.first + b);
+    const int g = find_grid(tile_start, p.w.ngrids, gt);
+    const DevGrid& G = grids[g];
+    const int64_t lt = gt - tile_start[g];
     const int nx = G.n[0], ny = G.n[1];
     const uint32_t lx = (uint32_t)(nx + 4);
     const int64_t total = (int64_t)lx * ny * G.n[2];
@@ -122,11 +134,18 @@ __global__ void __launch_bounds__(NT) k_sweep_x(SweepParams p) {
     const int k = (int)(row / (uint32_t)ny);
     const int i = face_index(il - 2, nx, G.mode[0], G.mode[1]);
     const int64_t rowq = (int64_t)(k + 2) * G.pxy + (int64_t)(j + 2) * G.px;
-    const T lam = (T)p.w.lam[g * 3 + 0];
+    // uniform base: the chunk's first row, aligned down to 64 cells
+    const uint32_t fu = (uint32_t)(lt * C < 2 ? 0 : lt * C - 2);
+    const uint32_t row0 = fu / lx;
+    const int64_t q0 = uniform(((int64_t)(row0 / (uint32_t)ny + 2) * G.pxy +
+                                (int64_t)(row0 % (uint32_t)ny + 2) * G.px) & ~int64_t(63));
+    const uint32_t lane_ld = Layout<LAY>::rel((uint32_t)(rowq + i + 2 - q0)) * (uint32_t)sizeof(T);
+    const uint32_t lane_st = Layout<LAY>::rel((uint32_t)(rowq + il - q0)) * (uint32_t)sizeof(T);
+    const T lam = (T)lamv[g * 3 + 0];
     const T hl = T(0.5) * lam;
 
     T u[5];
-    load_cell<T, LAY>(G.buf[p.in], rowq + i + 2, G.ptot, u);
+    load_cell_rel<T, LAY>(G.buf[p.in], q0, G.ptot, lane_ld, u);
 #pragma unroll
     for (int c = 0; c < 5; ++c) sA[c][tid] = u[c];
     __syncthreads();
@@ -157,10 +176,11 @@ __global__ void __launch_bounds__(NT) k_sweep_x(SweepParams p) {
     }
     __syncthreads();
     if (tid >= 2 && tid <= NT - 3 && valid && il >= 2 && il < nx + 2) {
-      T o[5];
+      T o[5], fp[5];
 #pragma unroll
-      for (int c = 0; c < 5; ++c) o[c] = u[c] - lam * (sB[c][tid + 1] - fx[c]);
-      store_cell<T, LAY>(G.buf[p.out], rowq + il, G.ptot, o);
+      for (int c = 0; c < 5; ++c) fp[c] = sB[c][tid + 1];
+      update(u, lam, fp, fx, o);
+      store_cell_rel<T, LAY>(G.buf[p.out], q0, G.ptot, lane_st, o);
     }
     __syncthreads();
   }
@@ -170,106 +190,156 @@ __global__ void __launch_bounds__(NT) k_sweep_x(SweepParams p) {
 // y / z sweeps
 // ---------------------------------------------------------------------------
 
-// Tile = (chunk of blockDim.x consecutive cells of the plane across the sweep,
-// x fastest) x (segment of p.seg cells along D).  Segment index runs fastest
-// so that the segments of one column, which overlap by four cells, are
-// processed by neighbouring workgroups.
-template <typename T, int LAY, int D>
-__global__ void __launch_bounds__(256) k_sweep_yz(SweepParams p) {
+// Tile = (chunk of blockDim.x column groups of the plane across the sweep, x
+// fastest) x (segment of p.seg cells along D).  A column group is COLS
+// adjacent cells along x that one thread advances together: in SoA and AoSoA
+// their values move as one 8- or 16-byte access per component, which the
+// memory pipeline sustains far better than 4-byte accesses.  Segment index
+// runs fastest so that the segments of one column, which overlap by four
+// cells, are processed by neighbouring workgroups.
+//
+// Each thread marches along D.  The cells it holds live in a ring of
+// YZ_RING register slots: U_j (the cell being written), U_{j+1}, U_{j+2} (the
+// stencil of the reconstruction at j+1) and YZ_RING - 3 cells loaded ahead,
+// so every load is issued YZ_RING - 3 iterations before its first use.  The
+// loop is unrolled by the ring length, which makes every slot index a
+// compile-time constant.
+//
+// Addressing: all lanes of a tile sit at the same index j along D, so the row
+// address of component c at j is wave-uniform (scalar registers) and each
+// lane adds a fixed 32-bit offset for the whole tile.
+#ifndef RFV_YZ_RING
+#define RFV_YZ_RING 5
+#endif
+template <typename T, int LAY, int D, bool FUSE, int COLS>
+__global__ void __launch_bounds__(256) k_sweep_yz(SweepParams p, const DevGrid* __restrict__ grids,
+                                                  const int64_t* __restrict__ tile_start,
+                                                  const double* __restrict__ lamv) {
+  constexpr int K = RFV_YZ_RING;  // ring slots
+  static_assert(K >= 4, "ring must hold the stencil and one cell ahead");
   __shared__ T red[3 * 16];
   const int nt = blockDim.x;
   const int tid = threadIdx.x;
   for (int64_t b = xcd_order(blockIdx.x, gridDim.x); b < p.tiles.count; b += gridDim.x) {
-    const int64_t gt = p.tiles.first + b;
-    const int g = find_grid(p.tiles.tile_start, p.w.ngrids, gt);
-    const DevGrid& G = p.w.grids[g];
-    const int64_t lt = gt - p.tiles.tile_start[g];
-    const int na = G.n[0];
-    const int nb = G.n[D == 1 ? 2 : 1];
+    const int64_t gt = uniform(p.tiles.first + b);
+    const int g = find_grid(tile_start, p.w.ngrids, gt);
+    const DevGrid& G = grids[g];
+    const int64_t lt = gt - tile_start[g];
+    const uint32_t na = G.n[0];
+    const uint32_t nb = G.n[D == 1 ? 2 : 1];
     const int nd = G.n[D];
     const int nseg = (nd + p.seg - 1) / p.seg;
     const int64_t chunk = lt / nseg;
     const int s = (int)(lt - chunk * nseg);
-    const uint32_t nplane = (uint32_t)na * (uint32_t)nb;
-    const uint32_t fl = (uint32_t)(chunk * nt + tid);
-    const bool active = fl < nplane;
-    const uint32_t fc = active ? fl : nplane - 1;
-    const int ia = (int)(fc % (uint32_t)na);
-    const int ib = (int)(fc / (uint32_t)na);
+    const uint32_t npr = (na + COLS - 1) / COLS;  // column groups per row
+    const uint32_t ngroups = npr * nb;
+    const uint32_t f0 = (uint32_t)(chunk * nt);
+    const uint32_t fl = f0 + tid;
+    const bool active = fl < ngroups;
+    const uint32_t fc = active ? fl : ngroups - 1;
+    const uint32_t ib = fc / npr, ia = (fc - ib * npr) * COLS;
+    const uint32_t ib0 = f0 / npr, ia0 = (f0 - ib0 * npr) * COLS;
+    bool act[COLS];
+#pragma unroll
+    for (int k = 0; k < COLS; ++k) act[k] = active && ia + k < na;
+    const int64_t across = D == 1 ? G.pxy : G.px;
     const int64_t stride = D == 1 ? G.px : G.pxy;
-    const int64_t base = (int64_t)(ia + 2) + (int64_t)(ib + 2) * (D == 1 ? G.pxy : G.px);
+    const int64_t qlane = (int64_t)(ia + 2) + (int64_t)(ib + 2) * across;
+    const int64_t qfirst = (int64_t)(ia0 + 2) + (int64_t)(ib0 + 2) * across;
+    const int64_t q0 = uniform(qfirst & ~int64_t(63));
+    const uint32_t lane = Layout<LAY>::rel((uint32_t)(qlane - q0)) * (uint32_t)sizeof(T);
     const int mlo = G.mode[2 * D], mhi = G.mode[2 * D + 1];
     const void* src = G.buf[p.in];
     void* dst = G.buf[p.out];
-    const T lam = (T)p.w.lam[g * 3 + D];
+    const T lam = (T)lamv[g * 3 + D];
     const T hl = T(0.5) * lam;
     const int j0 = s * p.seg;
     const int len = min(p.seg, nd - j0);
+    const int jlast = j0 + len + 1;  // last cell the segment reads
+    const int64_t ptot = G.ptot;
 
-    T w0[5], w1[5], w2[5], dprev[5], dnext[5], bl[5], br[5], brp[5], fprev[5];
-    load_cell<T, LAY>(src, base + (face_index(j0 - 2, nd, mlo, mhi) + 2) * stride, G.ptot, w0);
-    load_cell<T, LAY>(src, base + (face_index(j0 - 1, nd, mlo, mhi) + 2) * stride, G.ptot, w1);
-    load_cell<T, LAY>(src, base + (face_index(j0, nd, mlo, mhi) + 2) * stride, G.ptot, w2);
+    auto row = [&](int j) -> int64_t {
+      return q0 + (int64_t)(face_index(min(j, jlast), nd, mlo, mhi) + 2) * stride;
+    };
+
+    // slot of cell j' is (j' - j0 + 2) mod K
+    T ring[K][COLS][5];
+    T dprev[COLS][5], dnext[5], bl[5], br[COLS][5], brp[COLS][5], fprev[COLS][5];
 #pragma unroll
-    for (int c = 0; c < 5; ++c) {
-      dprev[c] = w1[c] - w0[c];
-      dnext[c] = w2[c] - w1[c];
+    for (int k = 0; k < K; ++k) load_group<T, LAY, COLS>(src, row(j0 - 2 + k), ptot, lane, ring[k]);
+#pragma unroll
+    for (int m = 0; m < COLS; ++m) {
+#pragma unroll
+      for (int c = 0; c < 5; ++c) {
+        dprev[m][c] = ring[1][m][c] - ring[0][m][c];
+        dnext[c] = ring[2][m][c] - ring[1][m][c];
+      }
+      hancock<T, D>(ring[1][m], dprev[m], dnext, hl, bl, brp[m]);   // cell j0 - 1
+#pragma unroll
+      for (int c = 0; c < 5; ++c) {
+        dprev[m][c] = dnext[c];
+        dnext[c] = ring[3][m][c] - ring[2][m][c];
+      }
+      hancock<T, D>(ring[2][m], dprev[m], dnext, hl, bl, br[m]);    // cell j0
+      hllc<T, D>(brp[m], bl, fprev[m]);                             // face j0 - 1/2
+#pragma unroll
+      for (int c = 0; c < 5; ++c) {
+        brp[m][c] = br[m][c];
+        dprev[m][c] = dnext[c];
+      }
     }
-    hancock<T, D>(w1, dprev, dnext, hl, bl, brp);          // cell j0 - 1
-#pragma unroll
-    for (int c = 0; c < 5; ++c) {
-      w0[c] = w1[c];
-      w1[c] = w2[c];
-      dprev[c] = dnext[c];
-    }
-    load_cell<T, LAY>(src, base + (face_index(j0 + 1, nd, mlo, mhi) + 2) * stride, G.ptot, w2);
-#pragma unroll
-    for (int c = 0; c < 5; ++c) dnext[c] = w2[c] - w1[c];
-    hancock<T, D>(w1, dprev, dnext, hl, bl, br);           // cell j0
-    hllc<T, D>(brp, bl, fprev);                            // face j0 - 1/2
-#pragma unroll
-    for (int c = 0; c < 5; ++c) {
-      brp[c] = br[c];
-      w0[c] = w1[c];
-      w1[c] = w2[c];
-      dprev[c] = dnext[c];
-    }
+    load_group<T, LAY, COLS>(src, row(j0 + K - 2), ptot, lane, ring[0]);
 
     T smax[3] = {T(0), T(0), T(0)};
     bool bad = false;
-    // invariant at the top: w0 = U_j, w1 = U_{j+1}, dprev = U_{j+1} - U_j,
-    // brp = Ub^R_j, fprev = F_{j-1/2}
-    for (int o = 0; o < len; ++o) {
-      const int j = j0 + o;
-      load_cell<T, LAY>(src, base + (face_index(j + 2, nd, mlo, mhi) + 2) * stride, G.ptot, w2);
+    // At iteration o (cell j = j0 + o): ring[(o+2)%K] = U_j, ring[(o+3)%K] = U_{j+1},
+    // ring[(o+4)%K] = U_{j+2}; dprev = U_{j+1} - U_j, brp = Ub^R_j, fprev = F_{j-1/2}.
+    // The slot of U_{j-1}, dead now, receives U_{j+K-1}.
+    for (int o0 = 0; o0 < len; o0 += K) {
 #pragma unroll
-      for (int c = 0; c < 5; ++c) dnext[c] = w2[c] - w1[c];
-      hancock<T, D>(w1, dprev, dnext, hl, bl, br);         // cell j + 1
-      T fcur[5], out[5];
-      hllc<T, D>(brp, bl, fcur);                           // face j + 1/2
+      for (int k = 0; k < K; ++k) {
+        const int o = o0 + k;
+        if (o >= len) break;
+        const int j = j0 + o;
+        load_group<T, LAY, COLS>(src, row(j + K - 1), ptot, lane, ring[(k + 1) % K]);
+        T out[COLS][5];
 #pragma unroll
-      for (int c = 0; c < 5; ++c) out[c] = w0[c] - lam * (fcur[c] - fprev[c]);
-      if (active) store_cell<T, LAY>(dst, base + (int64_t)(j + 2) * stride, G.ptot, out);
-      if (p.fuse_s) {
-        T sc[3];
-        bool b_ = false;
-        wavespeeds(out, sc, b_);
-        if (active) {
+        for (int m = 0; m < COLS; ++m) {
+          const T* uj = ring[(k + 2) % K][m];
+          const T* uj1 = ring[(k + 3) % K][m];
+          const T* uj2 = ring[(k + 4) % K][m];
 #pragma unroll
-          for (int d = 0; d < 3; ++d) smax[d] = __builtin_fmax(smax[d], sc[d]);
-          bad |= b_;
+          for (int c = 0; c < 5; ++c) dnext[c] = uj2[c] - uj1[c];
+          hancock<T, D>(uj1, dprev[m], dnext, hl, bl, br[m]);       // cell j + 1
+          T fcur[5];
+          hllc<T, D>(brp[m], bl, fcur);                             // face j + 1/2
+          update(uj, lam, fcur, fprev[m], out[m]);
+#pragma unroll
+          for (int c = 0; c < 5; ++c) {
+            fprev[m][c] = fcur[c];
+            brp[m][c] = br[m][c];
+            dprev[m][c] = dnext[c];
+          }
+        }
+        if (act[0])
+          store_group<T, LAY, COLS>(dst, q0 + (int64_t)(j + 2) * stride, ptot, lane, out,
+                                    act[COLS - 1]);
+        if (FUSE) {
+#pragma unroll
+          for (int m = 0; m < COLS; ++m) {
+            T sc[3];
+            bool b_ = false;
+            wavespeeds(out[m], sc, b_);
+            if (act[m]) {
+#pragma unroll
+              for (int d = 0; d < 3; ++d) smax[d] = bits_max(smax[d], sc[d]);
+              bad |= b_;
+            }
+          }
         }
       }
-#pragma unroll
-      for (int c = 0; c < 5; ++c) {
-        fprev[c] = fcur[c];
-        brp[c] = br[c];
-        w0[c] = w1[c];
-        w1[c] = w2[c];
-        dprev[c] = dnext[c];
-      }
     }
-    if (p.fuse_s) fold_wavespeeds<T>(smax, bad, p.w.s_acc + 3 * G.group, p.w.flag, red);
+    if (FUSE) fold_wavespeeds<T>(smax, bad, p.w.s_acc + 3 * G.group, p.w.flag, red);
   }
 }
 
@@ -279,13 +349,15 @@ __global__ void __launch_bounds__(256) k_sweep_yz(SweepParams p) {
 
 template <typename T, int LAY>
 __global__ void __launch_bounds__(WS_BLOCK) k_wavespeed(Work w, int in, TileRange tr,
-                                                        unsigned long long* s_out) {
+                                                        unsigned long long* s_out,
+                                                        const DevGrid* __restrict__ grids,
+                                                        const int64_t* __restrict__ tile_start) {
   __shared__ T red[3 * 16];
   for (int64_t b = xcd_order(blockIdx.x, gridDim.x); b < tr.count; b += gridDim.x) {
-    const int64_t gt = tr.first + b;
-    const int g = find_grid(tr.tile_start, w.ngrids, gt);
-    const DevGrid& G = w.grids[g];
-    const int64_t lt = gt - tr.tile_start[g];
+    const int64_t gt = uniform(tr.first + b);
+    const int g = find_grid(tile_start, w.ngrids, gt);
+    const DevGrid& G = grids[g];
+    const int64_t lt = gt - tile_start[g];
     const uint32_t nx = G.n[0], ny = G.n[1];
     const uint32_t ncell = nx * ny * (uint32_t)G.n[2];
     T smax[3] = {T(0), T(0), T(0)};
@@ -303,7 +375,7 @@ __global__ void __launch_bounds__(WS_BLOCK) k_wavespeed(Work w, int in, TileRang
         load_cell<T, LAY>(G.buf[in], q, G.ptot, u);
         wavespeeds(u, s, b_);
 #pragma unroll
-        for (int d = 0; d < 3; ++d) smax[d] = __builtin_fmax(smax[d], s[d]);
+        for (int d = 0; d < 3; ++d) smax[d] = bits_max(smax[d], s[d]);
         bad |= b_;
       }
     }
@@ -560,9 +632,9 @@ int64_t tiles_x(const ripple_fv_grid& g, int x_block) {
   return (total + c - 1) / c;
 }
 
-int64_t tiles_yz(const ripple_fv_grid& g, int axis, int yz_block, int yz_segment) {
-  const int64_t nplane = (int64_t)g.n[0] * g.n[axis == 1 ? 2 : 1];
-  const int64_t nchunk = (nplane + yz_block - 1) / yz_block;
+int64_t tiles_yz(const ripple_fv_grid& g, int axis, int yz_block, int yz_segment, int yz_cols) {
+  const int64_t ngroups = (int64_t)((g.n[0] + yz_cols - 1) / yz_cols) * g.n[axis == 1 ? 2 : 1];
+  const int64_t nchunk = (ngroups + yz_block - 1) / yz_block;
   const int64_t nseg = (g.n[axis] + yz_segment - 1) / yz_segment;
   return nchunk * nseg;
 }
@@ -573,18 +645,36 @@ int64_t tiles_ws(const ripple_fv_grid& g) {
   return (ncell + per - 1) / per;
 }
 
+template <typename T, int LAY, int COLS>
+static hipError_t sweep_yz_cols(int axis, const Tiling& tl, const SweepParams& p, int blocks,
+                                hipStream_t s) {
+  const DevGrid* G = p.w.grids;
+  const int64_t* TS = p.tiles.tile_start;
+  const double* L = p.w.lam;
+  if (axis == 1)
+    hipLaunchKernelGGL((k_sweep_yz<T, LAY, 1, false, COLS>), dim3(blocks), dim3(tl.yz_block), 0, s, p, G, TS, L);
+  else if (p.fuse_s)
+    hipLaunchKernelGGL((k_sweep_yz<T, LAY, 2, true, COLS>), dim3(blocks), dim3(tl.yz_block), 0, s, p, G, TS, L);
+  else
+    hipLaunchKernelGGL((k_sweep_yz<T, LAY, 2, false, COLS>), dim3(blocks), dim3(tl.yz_block), 0, s, p, G, TS, L);
+  return hipGetLastError();
+}
+
 template <typename T, int LAY>
 static hipError_t sweep_typed(int axis, const Tiling& tl, const SweepParams& p, int blocks,
                               hipStream_t s) {
+  const DevGrid* G = p.w.grids;
+  const int64_t* TS = p.tiles.tile_start;
+  const double* L = p.w.lam;
   if (axis == 0) {
     if (tl.x_block == 128)
-      hipLaunchKernelGGL((k_sweep_x<T, LAY, 128>), dim3(blocks), dim3(128), 0, s, p);
+      hipLaunchKernelGGL((k_sweep_x<T, LAY, 128>), dim3(blocks), dim3(128), 0, s, p, G, TS, L);
     else
-      hipLaunchKernelGGL((k_sweep_x<T, LAY, 256>), dim3(blocks), dim3(256), 0, s, p);
-  } else if (axis == 1) {
-    hipLaunchKernelGGL((k_sweep_yz<T, LAY, 1>), dim3(blocks), dim3(tl.yz_block), 0, s, p);
+      hipLaunchKernelGGL((k_sweep_x<T, LAY, 256>), dim3(blocks), dim3(256), 0, s, p, G, TS, L);
+  } else if (tl.yz_cols == 2) {
+    return sweep_yz_cols<T, LAY, 2>(axis, tl, p, blocks, s);
   } else {
-    hipLaunchKernelGGL((k_sweep_yz<T, LAY, 2>), dim3(blocks), dim3(tl.yz_block), 0, s, p);
+    return sweep_yz_cols<T, LAY, 1>(axis, tl, p, blocks, s);
   }
   return hipGetLastError();
 }
@@ -612,11 +702,11 @@ template <typename T>
 static hipError_t ws_lay(int lay, const Work& w, int in, TileRange tr, unsigned long long* so,
                          int blocks, hipStream_t s) {
   switch (lay) {
-    case LAY_AOS: hipLaunchKernelGGL((k_wavespeed<T, LAY_AOS>), dim3(blocks), dim3(WS_BLOCK), 0, s, w, in, tr, so); break;
-    case LAY_SOA: hipLaunchKernelGGL((k_wavespeed<T, LAY_SOA>), dim3(blocks), dim3(WS_BLOCK), 0, s, w, in, tr, so); break;
-    case LAY_AOSOA16: hipLaunchKernelGGL((k_wavespeed<T, LAY_AOSOA16>), dim3(blocks), dim3(WS_BLOCK), 0, s, w, in, tr, so); break;
-    case LAY_AOSOA32: hipLaunchKernelGGL((k_wavespeed<T, LAY_AOSOA32>), dim3(blocks), dim3(WS_BLOCK), 0, s, w, in, tr, so); break;
-    default: hipLaunchKernelGGL((k_wavespeed<T, LAY_AOSOA64>), dim3(blocks), dim3(WS_BLOCK), 0, s, w, in, tr, so); break;
+    case LAY_AOS: hipLaunchKernelGGL((k_wavespeed<T, LAY_AOS>), dim3(blocks), dim3(WS_BLOCK), 0, s, w, in, tr, so, w.grids, tr.tile_start); break;
+    case LAY_SOA: hipLaunchKernelGGL((k_wavespeed<T, LAY_SOA>), dim3(blocks), dim3(WS_BLOCK), 0, s, w, in, tr, so, w.grids, tr.tile_start); break;
+    case LAY_AOSOA16: hipLaunchKernelGGL((k_wavespeed<T, LAY_AOSOA16>), dim3(blocks), dim3(WS_BLOCK), 0, s, w, in, tr, so, w.grids, tr.tile_start); break;
+    case LAY_AOSOA32: hipLaunchKernelGGL((k_wavespeed<T, LAY_AOSOA32>), dim3(blocks), dim3(WS_BLOCK), 0, s, w, in, tr, so, w.grids, tr.tile_start); break;
+    default: hipLaunchKernelGGL((k_wavespeed<T, LAY_AOSOA64>), dim3(blocks), dim3(WS_BLOCK), 0, s, w, in, tr, so, w.grids, tr.tile_start); break;
   }
   return hipGetLastError();
 }

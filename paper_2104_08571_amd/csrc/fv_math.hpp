@@ -14,11 +14,12 @@
 // Precision notes.  FP32 uses the hardware reciprocal and square root
 // (v_rcp_f32, v_sqrt_f32, 1 ulp) and v_med3_f32 for minmod; FP64 uses IEEE
 // division and square root.  Each density is inverted once per state and
-// velocities and kinetic energy are formed by multiplication.  Expression
-// order otherwise follows the textbook formulas; the build disables
-// floating-point contraction, so every kernel variant (layout, tiling, batch
-// or single grid) performs the same operations on a cell and produces the
-// same bits.
+// velocities and kinetic energy are formed by multiplication.  The build
+// disables implicit contraction; fused multiply-adds appear only where written
+// (fma_ below), so every inlined copy of these functions -- in every layout,
+// tiling, batched or partitioned variant, prologue or loop body -- performs
+// the same operations on a cell and produces the same bits.  Expression order
+// otherwise follows the textbook formulas.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -48,13 +49,17 @@ template <> struct Arith<double> {
   }
 };
 
+__device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 template <typename T> __device__ __forceinline__ T gamma_() { return T(1.4); }
 template <typename T> __device__ __forceinline__ T gamma_m1() { return T(1.4) - T(1); }
 
 // p = (gamma - 1) (E - |m|^2 / (2 rho)), given rinv = 1 / rho.
 template <typename T>
 __device__ __forceinline__ T pressure(const T u[5], T rinv) {
-  const T kinetic = T(0.5) * (u[1] * u[1] + u[2] * u[2] + u[3] * u[3]) * rinv;
+  const T m2 = fma_(u[3], u[3], fma_(u[2], u[2], u[1] * u[1]));
+  const T kinetic = T(0.5) * m2 * rinv;
   return gamma_m1<T>() * (u[4] - kinetic);
 }
 
@@ -65,7 +70,7 @@ __device__ __forceinline__ void flux(const T u[5], T un, T p, T f[5]) {
   f[1] = u[1] * un;
   f[2] = u[2] * un;
   f[3] = u[3] * un;
-  f[1 + D] += p;
+  f[1 + D] = fma_(u[1 + D], un, p);
   f[4] = un * (u[4] + p);
 }
 
@@ -80,8 +85,8 @@ __device__ __forceinline__ void hancock(const T u0[5], const T dm[5], const T dp
 #pragma unroll
   for (int c = 0; c < 5; ++c) {
     const T s = Arith<T>::minmod(dm[c], dp[c]);
-    ul[c] = u0[c] - T(0.5) * s;
-    ur[c] = u0[c] + T(0.5) * s;
+    ul[c] = fma_(T(-0.5), s, u0[c]);  // s/2 is exact: one rounding, as u0 - s/2
+    ur[c] = fma_(T(0.5), s, u0[c]);
   }
   const T rl = Arith<T>::recip(ul[0]);
   const T rr = Arith<T>::recip(ur[0]);
@@ -90,9 +95,9 @@ __device__ __forceinline__ void hancock(const T u0[5], const T dm[5], const T dp
   flux<T, D>(ur, ur[1 + D] * rr, pressure(ur, rr), fr);
 #pragma unroll
   for (int c = 0; c < 5; ++c) {
-    const T h = hl * (fl[c] - fr[c]);
-    bl[c] = ul[c] + h;
-    br[c] = ur[c] + h;
+    const T d = fl[c] - fr[c];
+    bl[c] = fma_(hl, d, ul[c]);
+    br[c] = fma_(hl, d, ur[c]);
   }
 }
 
@@ -113,8 +118,9 @@ __device__ __forceinline__ void hllc(const T ul[5], const T ur[5], T f[5]) {
   const T cR = A::root(gamma_<T>() * pR * rr);
   const T SL = __builtin_fmin(uL - cL, uR - cR);
   const T SR = __builtin_fmax(uL + cL, uR + cR);
-  const T num = pR - pL + ul[0] * uL * (SL - uL) - ur[0] * uR * (SR - uR);
-  const T den = ul[0] * (SL - uL) - ur[0] * (SR - uR);
+  const T aL = SL - uL, aR = SR - uR;
+  const T num = fma_(-(ur[0] * uR), aR, fma_(ul[0] * uL, aL, pR - pL));
+  const T den = fma_(ul[0], aL, -(ur[0] * aR));
   const T Ss = A::quot(num, den);
 
   const bool left = (T(0) <= SL) || (T(0) <= Ss);
@@ -137,9 +143,16 @@ __device__ __forceinline__ void hllc(const T ul[5], const T ur[5], T f[5]) {
   us[2] = factor * (uk[2] * rk);
   us[3] = factor * (uk[3] * rk);
   us[1 + D] = factor * Ss;
-  us[4] = factor * (uk[4] * rk + (Ss - unk) * (Ss + A::quot(pk, Ak)));
+  us[4] = factor * fma_(Ss - unk, Ss + A::quot(pk, Ak), uk[4] * rk);
 #pragma unroll
-  for (int c = 0; c < 5; ++c) f[c] = supersonic ? fk[c] : fk[c] + Sk * (us[c] - uk[c]);
+  for (int c = 0; c < 5; ++c) f[c] = supersonic ? fk[c] : fma_(Sk, us[c] - uk[c], fk[c]);
+}
+
+// Conservative update U' = U - lam (F_{i+1/2} - F_{i-1/2}).
+template <typename T>
+__device__ __forceinline__ void update(const T u[5], T lam, const T fp[5], const T fm[5], T out[5]) {
+#pragma unroll
+  for (int c = 0; c < 5; ++c) out[c] = fma_(-lam, fp[c] - fm[c], u[c]);
 }
 
 // |u_d| + c for d = x, y, z; `bad` when rho <= 0, p <= 0 or a value is not finite.

@@ -51,6 +51,8 @@ class Grid(ctypes.Structure):
         ("yz_block", ctypes.c_int32),
         ("yz_segment", ctypes.c_int32),
         ("persist", ctypes.c_int32),
+        ("yz_cols", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
         ("pitch", ctypes.c_int64 * 3),
         ("bytes", ctypes.c_int64),
     ]
@@ -59,7 +61,7 @@ class Grid(ctypes.Structure):
         return (f"Grid(n={list(self.n)}, bc={list(self.bc)}, layout={self.layout}, "
                 f"dtype={self.dtype}, aosoa_w={self.aosoa_w}, group={self.group}, "
                 f"nbr={list(self.nbr)}, tiling=({self.x_block}, {self.yz_block}, "
-                f"{self.yz_segment}, {self.persist}), bytes={self.bytes})")
+                f"{self.yz_segment}, {self.persist}, {self.yz_cols}), bytes={self.bytes})")
 
 
 class RippleFVError(RuntimeError):
@@ -259,7 +261,7 @@ def call(name, *args):
 # -- descriptor helper ----------------------------------------------------------
 
 def make_grid(n, dtype=F64, layout=SOA, bc=(TRANSMISSIVE,) * 3, dx=None, aosoa_w=0,
-              group=-1, nbr=(-1,) * 6, tiling=(0, 0, 0, 0)):
+              group=-1, nbr=(-1,) * 6, tiling=(0, 0, 0, 0, 0)):
     """A ripple_fv_grid with pitch and bytes filled (ripple_fv_grid_init)."""
     g = Grid()
     n = [int(v) for v in n]
@@ -273,7 +275,8 @@ def make_grid(n, dtype=F64, layout=SOA, bc=(TRANSMISSIVE,) * 3, dx=None, aosoa_w
     g.dtype = int(dtype)
     g.aosoa_w = int(aosoa_w)
     g.group = int(group)
-    g.x_block, g.yz_block, g.yz_segment, g.persist = [int(v) for v in tiling]
+    tiling = list(tiling) + [0] * (5 - len(tiling))
+    g.x_block, g.yz_block, g.yz_segment, g.persist, g.yz_cols = [int(v) for v in tiling]
     return ripple_fv_grid_init(g)
 
 

@@ -83,3 +83,24 @@ def assert_parity(gpu, ref, tol, what=""):
 
 def unit_dx(n):
     return [1.0 / n[0], 1.0 / n[1], 1.0 / n[2]]
+
+
+class RawDeviceBuffer:
+    """An exact-size hipMalloc allocation (torch's caching allocator carves
+    tensors out of larger segments, which hides undersized buffers from the
+    library's allocation-range check)."""
+
+    def __init__(self, nbytes):
+        import ctypes
+        self._hip = ctypes.CDLL("libamdhip64.so")
+        self.ptr = ctypes.c_void_p()
+        err = self._hip.hipMalloc(ctypes.byref(self.ptr), ctypes.c_size_t(int(nbytes)))
+        assert err == 0, f"hipMalloc failed: {err}"
+
+    def data_ptr(self):
+        return int(self.ptr.value)
+
+    def free(self):
+        if self.ptr:
+            self._hip.hipFree(self.ptr)
+            self.ptr = None

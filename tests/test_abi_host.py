@@ -30,14 +30,16 @@ def test_library_exports_every_symbol():
 
 
 def test_grid_struct_size():
-    # 3*4 + 3*4 + 3*8 + 4*4 + 6*4 + 4*4 + 3*8 + 8, no padding holes
-    assert ctypes.sizeof(R.Grid) == 136
+    # 3*4 + 3*4 + 3*8 + 4*4 + 6*4 + 6*4 + 3*8 + 8, no padding holes
+    assert ctypes.sizeof(R.Grid) == 144
 
 
 def test_grid_init_pitches():
     g = R.make_grid((10, 7, 5), dtype=R.F32, layout=R.SOA)
     assert list(g.pitch) == [14, 11, 9]
     assert g.bytes == 14 * 11 * 9 * 5 * 4
+    g = R.make_grid((11, 7, 5), dtype=R.F32, layout=R.AOS)
+    assert list(g.pitch) == [16, 11, 9]  # row pitch rounded up to even
     g = R.make_grid((10, 7, 5), dtype=R.F64, layout=R.AOSOA, aosoa_w=16)
     assert list(g.pitch) == [16, 11, 9]
     assert g.bytes == 16 * 11 * 9 * 5 * 8
@@ -49,7 +51,8 @@ def test_grid_init_pitches():
     dict(n=(1, 4, 4)), dict(n=(4, 4, 0)), dict(dx=(0.0, 0.1, 0.1)), dict(dx=(-1.0, 0.1, 0.1)),
     dict(dtype=2), dict(layout=3), dict(layout=R.AOSOA, aosoa_w=8), dict(layout=R.SOA, aosoa_w=16),
     dict(bc=(0, 2, 0)), dict(tiling=(64, 0, 0, 0)), dict(tiling=(0, 512, 0, 0)),
-    dict(tiling=(0, 0, 2, 0)), dict(tiling=(0, 0, 0, -1)), dict(n=(2000, 2000, 2000)),
+    dict(tiling=(0, 0, 2, 0)), dict(tiling=(0, 0, 0, -1)), dict(tiling=(0, 0, 0, 0, 3)),
+    dict(n=(2000, 2000, 2000)),
 ])
 def test_grid_init_rejects(bad):
     kw = dict(n=(8, 8, 8))
