@@ -176,6 +176,31 @@ def run_partition_workload(steps, warmup):
     return out
 
 
+def copy_ceiling(nbytes=2 << 30, reps=20):
+    """Device-to-device copy rate of a plain copy kernel (torch's) over
+    `nbytes`-byte buffers: (read + write bytes) / time.  It is the practical
+    HBM ceiling that the sweeps are compared with, and the known-size program
+    against which rocprofv3's FETCH_SIZE / WRITE_SIZE counters are calibrated."""
+    import torch
+
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"bytes_per_copy": nbytes, "ms_per_copy": round(ms, 4),
+            "GBps_read_plus_write": round(2 * nbytes / (ms * 1e-3) / 1e9, 1)}
+
+
 def cpu_baseline(n, seed, steps):
     import numpy as np  # noqa: F401
 
@@ -203,18 +228,24 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--layout", default="soa", choices=["soa", "aos", "aosoa16", "aosoa32", "aosoa64"])
-    ap.add_argument("--tiling", default="0,0,0,0",
-                    help="x_block,yz_block,yz_segment,persist (0 = defaults)")
+    ap.add_argument("--tiling", default="0,0,0,0,0",
+                    help="x_block,yz_block,yz_segment,persist,yz_cols (0 = library default)")
     ap.add_argument("--no-f64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--cpu-steps", type=int, default=1,
                     help="oracle steps timed for cpu_baseline (0 = skip)")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the batched and partitioned workloads")
+    ap.add_argument("--copy-only", action="store_true",
+                    help="only run the plain-copy calibration (2 GiB, 20 copies) and print it")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(the partitioned path is measured as sub-blocks on one GPU)", file=sys.stderr)
         sys.exit(2)
+
+    if args.copy_only:
+        print(json.dumps({"copy_ceiling": copy_ceiling()}), flush=True)
+        return
 
     from paper_2104_08571_amd import ripple_fv as R
 
@@ -253,6 +284,9 @@ def main():
         print(f"[bench] fp64 {n}^3: {f64['gcell_updates_per_s']:.2f} Gcell-updates/s, "
               f"{f64['ms_per_step']:.3f} ms/step, kernels {f64['kernel_ms']}", file=sys.stderr,
               flush=True)
+
+    ceiling = copy_ceiling()
+    print(f"[bench] plain copy: {ceiling}", file=sys.stderr, flush=True)
 
     batch = part = None
     if not args.no_extra:
@@ -293,6 +327,7 @@ def main():
                      "traffic": traffic, "bytes_per_launch_algorithmic": f32["bytes_per_launch"],
                      "mean_launch_ms": round(f32["dominant_ms"], 4)},
         "cpu_baseline": base,
+        "copy_ceiling": ceiling,
     }
     if f64 is not None:
         out["f64"] = {"value": round(f64["gcell_updates_per_s"], 4), "unit": "Gcell-updates/s",
