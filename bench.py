@@ -118,7 +118,8 @@ def run_batch_workload(steps, warmup):
     out = {"grids": 64, "cells": cells, "tune_seconds": round(tune_s, 2),
            "chosen": {"layout": ["aos", "soa", "aosoa"][grids[0].layout], "aosoa_w": grids[0].aosoa_w,
                       "x_block": grids[0].x_block, "yz_block": grids[0].yz_block,
-                      "yz_segment": grids[0].yz_segment, "persist": grids[0].persist}}
+                      "yz_segment": grids[0].yz_segment, "persist": grids[0].persist,
+                      "yz_cols": grids[0].yz_cols, "split_xy": grids[0].split_xy}}
     for name, flags in (("batched_graph", R.RUN_GRAPH), ("batched_eager", R.RUN_EAGER),
                         ("per_grid", R.RUN_PER_GRID)):
         R.ripple_fv_run_batch(ctx, grids, pa, pb, warmup, 0.9, flags, stream)
@@ -228,8 +229,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--layout", default="soa", choices=["soa", "aos", "aosoa16", "aosoa32", "aosoa64"])
-    ap.add_argument("--tiling", default="0,0,0,0,0",
-                    help="x_block,yz_block,yz_segment,persist,yz_cols (0 = library default)")
+    ap.add_argument("--tiling", default="0,0,0,0,0,0",
+                    help="x_block,yz_block,yz_segment,persist,yz_cols,split_xy "
+                         "(0 = library default; split_xy 1 = separate x and y sweeps)")
     ap.add_argument("--no-f64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--cpu-steps", type=int, default=1,
                     help="oracle steps timed for cpu_baseline (0 = skip)")
@@ -261,7 +263,8 @@ def main():
         r = run_gpu(n, dtype, lay[0], lay[1], args.steps, args.warmup, seed, tiling)
         secs = r["seconds"]
         per_sweep = {k: (ms / cnt if cnt else None) for k, (ms, cnt) in r["profile"].items()}
-        sweeps = {k: per_sweep[k] for k in ("sweep_x", "sweep_y", "sweep_z")}
+        sweeps = {k: per_sweep[k] for k in ("sweep_x", "sweep_y", "sweep_z", "sweep_xy")
+                  if per_sweep[k]}
         dom = max(sweeps, key=lambda k: r["profile"][k][0])
         bytes_per_launch = 10 * s_bytes * cells
         achieved = bytes_per_launch / (sweeps[dom] * 1e-3) / 1e9

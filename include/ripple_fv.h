@@ -81,8 +81,12 @@ enum ripple_fv_run_flags {
 enum ripple_fv_kernel_kind {
   RIPPLE_FV_K_WAVESPEED = 0, RIPPLE_FV_K_DT = 1, RIPPLE_FV_K_SWEEP_X = 2,
   RIPPLE_FV_K_SWEEP_Y = 3, RIPPLE_FV_K_SWEEP_Z = 4, RIPPLE_FV_K_HALO = 5,
-  RIPPLE_FV_NKERNELS = 6
+  RIPPLE_FV_K_SWEEP_XY = 6, RIPPLE_FV_NKERNELS = 7
 };
+
+/* ripple_fv_sweep axis values: 0, 1, 2 = x, y, z; RIPPLE_FV_AXIS_XY = the x
+ * sweep followed by the y sweep in one fused pass. */
+#define RIPPLE_FV_AXIS_XY 3
 
 #define RIPPLE_FV_HALO 2
 #define RIPPLE_FV_NVAR 5
@@ -101,16 +105,34 @@ enum ripple_fv_kernel_kind {
  *  nbr      sub-block links per face (-x, +x, -y, +y, -z, +z): batch index of
  *           the neighbouring sub-block whose interior fills this face's
  *           padding, or -1 when the face is a physical boundary
- *  x_block, yz_block, yz_segment, persist, yz_cols   kernel tiling chosen by
- *           ripple_fv_batch_tune (0 = defaults); they never change results.
+ *  x_block, yz_block, yz_segment, persist, yz_cols, split_xy   kernel
+ *           tiling chosen by ripple_fv_batch_tune (0 = defaults); they never
+ *           change results.
  *           x_block: threads per workgroup of the x sweep (128, 256);
  *           yz_block: threads per workgroup of the y/z sweeps (64, 128, 256);
  *           yz_segment: cells each y/z thread advances (>= 4);
  *           persist: workgroups per CU of persistent launches (0 = one per tile);
  *           yz_cols: adjacent x cells per y/z thread (1, 2; 0 = 2 for FP32
- *           SoA/AoSoA, else 1)
+ *           SoA/AoSoA, else 1); in the fused x-y sweep, cells per thread of
+ *           workgroups of 512 / yz_cols threads (0 = 1 there);
+ *           split_xy: 0 = run the x and y sweeps as one fused pass wherever
+ *           a grid allows it (x and y faces not linked to sub-blocks, and
+ *           16 <= n[0] <= 512), 1 = always as two separate sweeps
  *  reserved must be 0
- *  pitch, bytes   OUT: padded extents (Px, Py, Pz) and bytes of one buffer */
+ *  x_origin OUT: padded x index of interior cell x = 0 (see below)
+ *  pitch, bytes   OUT: padded extents (Px, Py, Pz) and bytes of one buffer
+ *
+ * Storage of one buffer.  Cell (i, j, k), with each index in [-2, n + 2)
+ * (interior plus two padding layers per face), has the padded index
+ *     q = ((k + 2) * Py + (j + 2)) * Px + i + x_origin
+ * and component c (rho, rho u, rho v, rho w, E) of it sits at element
+ *     AOS    5 q + c
+ *     SOA    c * C + q
+ *     AOSOA  ((q / W) * 5 + c) * W + q % W      (W = aosoa_w)
+ * where C = bytes / (5 * element size) is the number of cell slots.  In SOA
+ * every interior row starts on a 128-byte boundary of the buffer (the buffer
+ * itself being 256-byte aligned), in AOSOA on a block boundary, so sweeps
+ * along y and z touch no partial cache lines at row ends. */
 typedef struct ripple_fv_grid {
   int32_t n[3];
   int32_t bc[3];
@@ -125,16 +147,22 @@ typedef struct ripple_fv_grid {
   int32_t yz_segment;
   int32_t persist;
   int32_t yz_cols;
+  int32_t split_xy;
   int32_t reserved;
+  int32_t x_origin;
   int64_t pitch[3];
   int64_t bytes;
 } ripple_fv_grid;
 
 typedef struct ripple_fv_ctx ripple_fv_ctx;
 
-/* Validate a descriptor and fill pitch[] and bytes.  Px = n[0] + 4 rounded
- * up to an even number (to a multiple of aosoa_w for AOSOA); Py = n[1] + 4;
- * Pz = n[2] + 4 (section "Tensors": padding is part of the tensor's storage).
+/* Validate a descriptor and fill x_origin, pitch[] and bytes (section
+ * "Tensors": padding is part of the tensor's storage).  Py = n[1] + 4,
+ * Pz = n[2] + 4.  AOS: x_origin = 2, Px = n[0] + 4 rounded up to even.
+ * SOA: x_origin = A, Px = n[0] + 4 rounded up to a multiple of A, where A =
+ * 128 bytes / element size (32 for F32, 16 for F64).  AOSOA: the same with
+ * A = max(128 bytes / element size, aosoa_w).  The cell-slot count
+ * C = Px Py Pz + x_origin rounded up to a multiple of 64.
  * E_INVALID on extents < 2, dx <= 0, unknown enums, bad aosoa_w, bad tiling
  * knobs, or a buffer size above 2^46 bytes. */
 ripple_fv_status ripple_fv_grid_init(ripple_fv_grid* g);
@@ -183,29 +211,34 @@ ripple_fv_status ripple_fv_max_wavespeed(ripple_fv_ctx* ctx, const ripple_fv_gri
 ripple_fv_status ripple_fv_sweep(ripple_fv_ctx* ctx, const ripple_fv_grid* g, int32_t axis,
                                  const void* u_in, void* u_out, double dt, void* stream);
 
-/* One full step: wave speeds -> dt = cfl * min_d dx_d / S_d (or the fixed
- * dt when dt > 0) -> sweep x (u_in -> u_out) -> sweep y (u_out -> u_in) ->
- * sweep z (u_in -> u_out).  The new state is in u_out; u_in is clobbered
- * (the paper's swap_in_out is left to the caller).  cfl in (0, 1].
- * dt_dev: optional device double receiving the dt used. */
-ripple_fv_status ripple_fv_step(ripple_fv_ctx* ctx, const ripple_fv_grid* g, void* u_in,
-                                void* u_out, double cfl, double dt, double* dt_dev,
+/* One full step of a whole grid, in place: wave speeds -> dt = cfl * min_d
+ * dx_d / S_d (or the fixed dt when dt > 0) -> sweeps x, y, z (section
+ * "Graphs": the paper's split Euler example, extended with z).  u holds the
+ * state before and after; work is a second buffer of g->bytes that the step
+ * clobbers (where the x and y sweeps run as one fused pass the step is
+ * u -> work -> u; otherwise the three sweeps ping-pong and the result is
+ * copied back).  cfl in (0, 1].  dt_dev: optional device double receiving
+ * the dt used. */
+ripple_fv_status ripple_fv_step(ripple_fv_ctx* ctx, const ripple_fv_grid* g, void* u,
+                                void* work, double cfl, double dt, double* dt_dev,
                                 void* stream);
 
 /* Advance n independent grids (or sub-blocks of partitioned domains) by
- * nsteps steps.  Every grid uses its group's dt from the CFL condition.
- * u_a[i], u_b[i]: the two buffers of grid i; the initial state is in u_a.
- * Each step runs x (a -> b), y (b -> a), z (a -> b) and then swaps the
- * roles, so after nsteps the result is in u_b when nsteps is odd and in u_a
- * when it is even.  Before each sweep along d, faces with a neighbour get
- * their padding copied from the neighbour's interior (the paper's
- * concurrent padded access, section "Tensor Data Dependencies").
- * All grids must share layout and dtype (else E_UNSUPPORTED).
+ * nsteps steps, in place.  Every grid uses its group's dt from the CFL
+ * condition.  u[i]: the state of grid i, before and after; work[i]: a second
+ * buffer of grids[i].bytes, clobbered.  A step runs the x and y sweeps as one
+ * fused pass (u -> work) and the z sweep (work -> u) where every grid allows
+ * the fusion (see split_xy); otherwise x (u -> work), y (work -> u), z
+ * (u -> work) with the roles swapped every step and one copy back to u after
+ * an odd number of steps.  Before each separate sweep along d, faces with a
+ * neighbour get their padding copied from the neighbour's interior (the
+ * paper's concurrent padded access, section "Tensor Data Dependencies").
+ * All grids must share layout, dtype and tiling knobs (else E_UNSUPPORTED).
  * flags: ripple_fv_run_flags.  The first call for a given set of grid
  * descriptors builds and caches a plan (workspaces, tile lists, graphs);
  * later calls with the same descriptors allocate nothing. */
 ripple_fv_status ripple_fv_run_batch(ripple_fv_ctx* ctx, int32_t n, const ripple_fv_grid* grids,
-                                     void* const* u_a, void* const* u_b, int32_t nsteps,
+                                     void* const* u, void* const* work, int32_t nsteps,
                                      double cfl, int32_t flags, void* stream);
 
 /* Time reached (t_host[i], since the start of the last ripple_fv_run_batch

@@ -29,13 +29,14 @@ struct Plan {
   int dtype = 0, lay = 0;
   Tiling tl{};
   std::vector<ripple_fv_grid> grids;
-  std::vector<int64_t> tiles[4];        // prefix: x, y, z, wave-speed tiles
+  bool fused = false;                   // x and y sweeps as one pass
+  std::vector<int64_t> tiles[5];        // prefix: x, y, z, wave-speed, fused x-y tiles
   std::vector<HaloTask> halo[3];
   int64_t halo_area[3] = {0, 0, 0};
   // device workspace (one allocation) and its views
   void* dmem = nullptr;
   DevGrid* d_grids = nullptr;
-  int64_t* d_tiles[4] = {nullptr, nullptr, nullptr, nullptr};
+  int64_t* d_tiles[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   HaloTask* d_halo[3] = {nullptr, nullptr, nullptr};
   double* d_lam = nullptr;
   double* d_t = nullptr;
@@ -112,7 +113,7 @@ bool valid_block(int v, std::initializer_list<int> allowed) {
 
 // Validate a descriptor and compute its pitches and size (ripple_fv_grid_init).
 ripple_fv_status grid_check(const ripple_fv_grid* g, int64_t pitch[3], int64_t* bytes,
-                            std::string* why) {
+                            int32_t* x_origin, std::string* why) {
   for (int d = 0; d < 3; ++d) {
     if (g->n[d] < 2) { *why = "extent < 2"; return RIPPLE_FV_E_INVALID; }
     if (!(g->dx[d] > 0.0) || !std::isfinite(g->dx[d])) { *why = "dx <= 0"; return RIPPLE_FV_E_INVALID; }
@@ -132,16 +133,24 @@ ripple_fv_status grid_check(const ripple_fv_grid* g, int64_t pitch[3], int64_t* 
   }
   if (!valid_block(g->x_block, {0, 128, 256}) || !valid_block(g->yz_block, {0, 64, 128, 256}) ||
       g->yz_segment < 0 || (g->yz_segment > 0 && g->yz_segment < 4) || g->yz_segment > 4096 ||
-      g->persist < 0 || g->persist > 64 || !valid_block(g->yz_cols, {0, 1, 2}) || g->reserved != 0) {
+      g->persist < 0 || g->persist > 64 || !valid_block(g->yz_cols, {0, 1, 2}) ||
+      !valid_block(g->split_xy, {0, 1}) || g->reserved != 0) {
     *why = "bad tiling knobs";
     return RIPPLE_FV_E_INVALID;
   }
-  // even row pitch: pairs of x cells start on 8-byte (FP32) / 16-byte (FP64) boundaries
-  int64_t px = (g->n[0] + 4 + 1) / 2 * 2;
-  if (g->layout == RIPPLE_FV_AOSOA) px = (px + g->aosoa_w - 1) / g->aosoa_w * g->aosoa_w;
-  const int64_t py = g->n[1] + 4, pz = g->n[2] + 4;
-  const int64_t cells = px * py * pz;
+  // AoS: even row pitch, so pairs of x cells start on 8-byte (FP32) / 16-byte
+  // (FP64) boundaries.  SoA / AoSoA: interior rows start on 128-byte lines
+  // (AoSoA: on a block), so y and z sweeps touch no partial lines.
   const int64_t elem = g->dtype == RIPPLE_FV_F32 ? 4 : 8;
+  int64_t align = 2, ox = HALO;
+  if (g->layout != RIPPLE_FV_AOS) {
+    align = 128 / elem;
+    if (g->layout == RIPPLE_FV_AOSOA && g->aosoa_w > align) align = g->aosoa_w;
+    ox = align;
+  }
+  const int64_t px = (g->n[0] + 4 + align - 1) / align * align;
+  const int64_t py = g->n[1] + 4, pz = g->n[2] + 4;
+  const int64_t cells = (px * py * pz + ox + 63) / 64 * 64;
   // 32-bit tile-local index spaces in the kernels
   if ((int64_t)(g->n[0] + 4) * g->n[1] * g->n[2] >= (int64_t(1) << 31) || cells >= (int64_t(1) << 40)) {
     *why = "grid too large";
@@ -153,6 +162,7 @@ ripple_fv_status grid_check(const ripple_fv_grid* g, int64_t pitch[3], int64_t* 
   pitch[1] = py;
   pitch[2] = pz;
   *bytes = b;
+  *x_origin = (int32_t)ox;
   return RIPPLE_FV_OK;
 }
 
@@ -166,6 +176,8 @@ Tiling tiling_of(const ripple_fv_grid& g) {
   // SoA/AoSoA); FP64 already moves 8 bytes per lane and would lose occupancy
   t.yz_cols = g.yz_cols ? g.yz_cols
                         : ((g.layout != RIPPLE_FV_AOS && g.dtype == RIPPLE_FV_F32) ? 2 : 1);
+  t.split_xy = g.split_xy;
+  t.xy_cols = g.yz_cols ? g.yz_cols : 1;
   return t;
 }
 
@@ -173,11 +185,12 @@ Tiling tiling_of(const ripple_fv_grid& g) {
 ripple_fv_status grid_ok(ripple_fv_ctx* ctx, const ripple_fv_grid* g) {
   if (!g) return fail(ctx, RIPPLE_FV_E_INVALID, "NULL grid");
   int64_t pitch[3], bytes;
+  int32_t ox;
   std::string why;
-  ripple_fv_status st = grid_check(g, pitch, &bytes, &why);
+  ripple_fv_status st = grid_check(g, pitch, &bytes, &ox, &why);
   if (st != RIPPLE_FV_OK) return fail(ctx, st, why);
   if (pitch[0] != g->pitch[0] || pitch[1] != g->pitch[1] || pitch[2] != g->pitch[2] ||
-      bytes != g->bytes)
+      bytes != g->bytes || ox != g->x_origin)
     return fail(ctx, RIPPLE_FV_E_INVALID, "grid not initialised (call ripple_fv_grid_init)");
   return RIPPLE_FV_OK;
 }
@@ -202,16 +215,21 @@ ripple_fv_status ptr_ok(ripple_fv_ctx* ctx, const void* p, int64_t bytes, int64_
   return RIPPLE_FV_OK;
 }
 
+// Cell slots per buffer (the SoA component stride).
+int64_t cell_slots(const ripple_fv_grid& g) {
+  return g.bytes / (5 * (g.dtype == RIPPLE_FV_F32 ? 4 : 8));
+}
+
 Desc desc_of(const ripple_fv_grid& g, const void* buf) {
   Desc d;
   d.buf = const_cast<void*>(buf);
   for (int i = 0; i < 3; ++i) d.n[i] = g.n[i];
   d.lay = lay_of(g);
   d.dtype = g.dtype;
-  d.pad_ = 0;
+  d.ox = g.x_origin;
   d.px = g.pitch[0];
   d.pxy = g.pitch[0] * g.pitch[1];
-  d.ptot = d.pxy * g.pitch[2];
+  d.ptot = cell_slots(g);
   return d;
 }
 
@@ -234,7 +252,7 @@ ripple_fv_status validate_batch(ripple_fv_ctx* ctx, int n, const ripple_fv_grid*
     if (G.dtype != g0.dtype || G.layout != g0.layout || G.aosoa_w != g0.aosoa_w)
       return fail(ctx, RIPPLE_FV_E_UNSUPPORTED, "grids of a batch must share layout and dtype");
     if (G.x_block != g0.x_block || G.yz_block != g0.yz_block || G.yz_segment != g0.yz_segment ||
-        G.persist != g0.persist || G.yz_cols != g0.yz_cols)
+        G.persist != g0.persist || G.yz_cols != g0.yz_cols || G.split_xy != g0.split_xy)
       return fail(ctx, RIPPLE_FV_E_UNSUPPORTED, "grids of a batch must share tiling knobs");
   }
   for (int g = 0; g < n; ++g) {
@@ -279,8 +297,12 @@ ripple_fv_status build_plan(ripple_fv_ctx* ctx, int n, const ripple_fv_grid* gri
   P->lay = lay_of(grids[0]);
   P->tl = tiling_of(grids[0]);
   P->grids.assign(grids, grids + n);
-  for (int k = 0; k < 4; ++k) P->tiles[k].assign(n + 1, 0);
+  P->fused = !P->tl.split_xy;
+  for (int g = 0; g < n; ++g) P->fused = P->fused && xy_eligible(grids[g], P->tl.xy_cols);
+  for (int k = 0; k < 5; ++k) P->tiles[k].assign(n + 1, 0);
   for (int g = 0; g < n; ++g) {
+    P->tiles[4][g + 1] = P->tiles[4][g] + (P->fused ? tiles_xy(grids[g], P->tl.yz_segment,
+                                                               P->tl.xy_cols) : 0);
     P->tiles[0][g + 1] = P->tiles[0][g] + tiles_x(grids[g], P->tl.x_block);
     P->tiles[1][g + 1] = P->tiles[1][g] + tiles_yz(grids[g], 1, P->tl.yz_block, P->tl.yz_segment,
                                                    P->tl.yz_cols);
@@ -322,15 +344,16 @@ ripple_fv_status build_plan(ripple_fv_ctx* ctx, int n, const ripple_fv_grid* gri
     }
     D.px = G.pitch[0];
     D.pxy = G.pitch[0] * G.pitch[1];
-    D.ptot = D.pxy * G.pitch[2];
+    D.ptot = cell_slots(G);
+    D.ox = G.x_origin;
     D.group = group_of(G, g);
   }
   // device workspace
   auto align = [](size_t v) { return (v + 255) & ~size_t(255); };
   size_t off = 0;
   const size_t o_grids = off; off = align(off + sizeof(DevGrid) * n);
-  size_t o_tiles[4];
-  for (int k = 0; k < 4; ++k) { o_tiles[k] = off; off = align(off + sizeof(int64_t) * (n + 1)); }
+  size_t o_tiles[5];
+  for (int k = 0; k < 5; ++k) { o_tiles[k] = off; off = align(off + sizeof(int64_t) * (n + 1)); }
   size_t o_halo[3];
   for (int k = 0; k < 3; ++k) { o_halo[k] = off; off = align(off + sizeof(HaloTask) * (P->halo[k].size() + 1)); }
   const size_t o_lam = off; off = align(off + sizeof(double) * 3 * n);
@@ -343,13 +366,13 @@ ripple_fv_status build_plan(ripple_fv_ctx* ctx, int n, const ripple_fv_grid* gri
   }
   char* base = static_cast<char*>(P->dmem);
   P->d_grids = reinterpret_cast<DevGrid*>(base + o_grids);
-  for (int k = 0; k < 4; ++k) P->d_tiles[k] = reinterpret_cast<int64_t*>(base + o_tiles[k]);
+  for (int k = 0; k < 5; ++k) P->d_tiles[k] = reinterpret_cast<int64_t*>(base + o_tiles[k]);
   for (int k = 0; k < 3; ++k) P->d_halo[k] = reinterpret_cast<HaloTask*>(base + o_halo[k]);
   P->d_lam = reinterpret_cast<double*>(base + o_lam);
   P->d_t = reinterpret_cast<double*>(base + o_t);
   P->d_dt = reinterpret_cast<double*>(base + o_dt);
   P->d_s = reinterpret_cast<unsigned long long*>(base + o_s);
-  for (int k = 0; k < 4; ++k)
+  for (int k = 0; k < 5; ++k)
     HIP_OR_FAIL(ctx, hipMemcpy(P->d_tiles[k], P->tiles[k].data(), sizeof(int64_t) * (n + 1),
                                hipMemcpyHostToDevice));
   for (int k = 0; k < 3; ++k)
@@ -479,6 +502,36 @@ ripple_fv_status enqueue_sweep(ripple_fv_ctx* ctx, Plan* P, Launcher& L, int axi
   return L.end(e1);
 }
 
+// Enqueue the fused x-then-y sweep (plans whose grids all allow it).
+ripple_fv_status enqueue_sweep_xy(ripple_fv_ctx* ctx, Plan* P, Launcher& L, int in, int out,
+                                  bool per_grid) {
+  SweepParams sp;
+  sp.w = P->work(ctx->flag);
+  sp.in = in;
+  sp.out = out;
+  sp.seg = P->tl.yz_segment;
+  sp.fuse_s = 0;
+  sp.tiles.tile_start = P->d_tiles[4];
+  hipEvent_t e1 = nullptr;
+  ripple_fv_status st = L.begin(RIPPLE_FV_K_SWEEP_XY, &e1);
+  if (st) return st;
+  const std::vector<int64_t>& pre = P->tiles[4];
+  if (per_grid) {
+    for (int g = 0; g < P->n; ++g) {
+      sp.tiles.first = pre[g];
+      sp.tiles.count = pre[g + 1] - pre[g];
+      LAUNCH_OR_FAIL(ctx, launch_sweep_xy(P->dtype, P->lay, P->tl, sp,
+                                          blocks_for(ctx, P->tl, sp.tiles.count), L.s));
+    }
+  } else {
+    sp.tiles.first = 0;
+    sp.tiles.count = pre[P->n];
+    LAUNCH_OR_FAIL(ctx, launch_sweep_xy(P->dtype, P->lay, P->tl, sp,
+                                        blocks_for(ctx, P->tl, sp.tiles.count), L.s));
+  }
+  return L.end(e1);
+}
+
 ripple_fv_status enqueue_halo(ripple_fv_ctx* ctx, Plan* P, Launcher& L, int axis, int buf) {
   if (P->halo[axis].empty()) return RIPPLE_FV_OK;
   hipEvent_t e1 = nullptr;
@@ -524,11 +577,18 @@ ripple_fv_status enqueue_dt(ripple_fv_ctx* ctx, Plan* P, Launcher& L, double cfl
 }
 
 // One step starting from buffer `cur`: dt, then x (cur -> oth), y (oth -> cur),
-// z (cur -> oth) with the new state's wave speeds folded into the slots.
+// z (cur -> oth) with the new state's wave speeds folded into the slots; or,
+// in a fused plan, x-y (cur -> oth) and z (oth -> cur).
 ripple_fv_status enqueue_step(ripple_fv_ctx* ctx, Plan* P, Launcher& L, int cur, double cfl,
                               double fixed_dt, double* dt_out, bool per_grid) {
   const int oth = 1 - cur;
   ripple_fv_status st = enqueue_dt(ctx, P, L, cfl, fixed_dt, 1, dt_out);
+  if (P->fused) {
+    if (!st) st = enqueue_sweep_xy(ctx, P, L, cur, oth, per_grid);
+    if (!st) st = enqueue_halo(ctx, P, L, 2, oth);
+    if (!st) st = enqueue_sweep(ctx, P, L, 2, oth, cur, 1, per_grid);
+    return st;
+  }
   if (!st) st = enqueue_halo(ctx, P, L, 0, cur);
   if (!st) st = enqueue_sweep(ctx, P, L, 0, cur, oth, 0, per_grid);
   if (!st) st = enqueue_halo(ctx, P, L, 1, oth);
@@ -538,13 +598,23 @@ ripple_fv_status enqueue_step(ripple_fv_ctx* ctx, Plan* P, Launcher& L, int cur,
   return st;
 }
 
+// After an odd number of separate-sweep steps the state is in the work
+// buffers: copy it back.
+ripple_fv_status enqueue_copy_back(ripple_fv_ctx* ctx, Plan* P, hipStream_t s) {
+  for (int g = 0; g < P->n; ++g)
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(P->h_grids[g].buf[0], P->h_grids[g].buf[1], P->grids[g].bytes,
+                                    hipMemcpyDeviceToDevice, s));
+  return RIPPLE_FV_OK;
+}
+
 ripple_fv_status capture_graph(ripple_fv_ctx* ctx, Plan* P, int nsteps, double cfl, bool per_grid,
                                hipGraphExec_t* out) {
   hipStream_t cs = ctx->cap_stream;
   HIP_OR_FAIL(ctx, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
   Launcher L{ctx, cs, false, {}, 0};
   ripple_fv_status st = RIPPLE_FV_OK;
-  for (int k = 0; k < nsteps && !st; ++k) st = enqueue_step(ctx, P, L, k & 1, cfl, 0.0, nullptr, per_grid);
+  for (int k = 0; k < nsteps && !st; ++k)
+    st = enqueue_step(ctx, P, L, P->fused ? 0 : (k & 1), cfl, 0.0, nullptr, per_grid);
   hipGraph_t graph = nullptr;
   hipError_t e = hipStreamEndCapture(cs, &graph);
   if (st) {
@@ -584,9 +654,9 @@ ripple_fv_status run(ripple_fv_ctx* ctx, int n, const ripple_fv_grid* grids, voi
   if (st) return st;
   if (!u_a || !u_b) return fail(ctx, RIPPLE_FV_E_INVALID, "NULL buffer list");
   for (int g = 0; g < n; ++g) {
-    if ((st = ptr_ok(ctx, u_a[g], grids[g].bytes, 256, "u_a"))) return st;
-    if ((st = ptr_ok(ctx, u_b[g], grids[g].bytes, 256, "u_b"))) return st;
-    if (u_a[g] == u_b[g]) return fail(ctx, RIPPLE_FV_E_INVALID, "u_a and u_b alias");
+    if ((st = ptr_ok(ctx, u_a[g], grids[g].bytes, 256, "u"))) return st;
+    if ((st = ptr_ok(ctx, u_b[g], grids[g].bytes, 256, "work"))) return st;
+    if (u_a[g] == u_b[g]) return fail(ctx, RIPPLE_FV_E_INVALID, "u and work alias");
   }
   Plan* P = nullptr;
   if ((st = build_plan(ctx, n, grids, &P))) return st;
@@ -609,11 +679,15 @@ ripple_fv_status run(ripple_fv_ctx* ctx, int n, const ripple_fv_grid* grids, voi
     }
     for (int k = 0; k + 1 < nsteps; k += 2) HIP_OR_FAIL(ctx, hipGraphLaunch(P->g2, s));
     if (nsteps & 1) HIP_OR_FAIL(ctx, hipGraphLaunch(P->g1, s));
+    // (the copy back stays outside the graphs: its pointers change with the buffers)
+    if (!P->fused && (nsteps & 1)) return enqueue_copy_back(ctx, P, s);
     return RIPPLE_FV_OK;
   }
   for (int k = 0; k < nsteps; ++k) {
-    if ((st = enqueue_step(ctx, P, L, k & 1, cfl, fixed_dt, dt_out, per_grid))) return st;
+    if ((st = enqueue_step(ctx, P, L, P->fused ? 0 : (k & 1), cfl, fixed_dt, dt_out, per_grid)))
+      return st;
   }
+  if (!P->fused && (nsteps & 1) && (st = enqueue_copy_back(ctx, P, s))) return st;
   return L.collect();
 }
 
@@ -628,11 +702,13 @@ extern "C" {
 ripple_fv_status ripple_fv_grid_init(ripple_fv_grid* g) {
   if (!g) return RIPPLE_FV_E_INVALID;
   int64_t pitch[3], bytes;
+  int32_t ox;
   std::string why;
-  ripple_fv_status st = grid_check(g, pitch, &bytes, &why);
+  ripple_fv_status st = grid_check(g, pitch, &bytes, &ox, &why);
   if (st) return st;
   for (int d = 0; d < 3; ++d) g->pitch[d] = pitch[d];
   g->bytes = bytes;
+  g->x_origin = ox;
   return RIPPLE_FV_OK;
 }
 
@@ -740,7 +816,8 @@ ripple_fv_status ripple_fv_sweep(ripple_fv_ctx* ctx, const ripple_fv_grid* g, in
   ripple_fv_status st = set_device(ctx);
   if (st) return st;
   if ((st = grid_ok(ctx, g))) return st;
-  if (axis < 0 || axis > 2) return fail(ctx, RIPPLE_FV_E_INVALID, "axis must be 0, 1 or 2");
+  if (axis < 0 || axis > RIPPLE_FV_AXIS_XY)
+    return fail(ctx, RIPPLE_FV_E_INVALID, "axis must be 0, 1, 2 or RIPPLE_FV_AXIS_XY");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(ctx, RIPPLE_FV_E_INVALID, "dt must be > 0");
   if ((st = ptr_ok(ctx, u_in, g->bytes, 256, "u_in"))) return st;
   if ((st = ptr_ok(ctx, u_out, g->bytes, 256, "u_out"))) return st;
@@ -758,11 +835,17 @@ ripple_fv_status ripple_fv_sweep(ripple_fv_ctx* ctx, const ripple_fv_grid* g, in
   if ((st = upload_buffers(ctx, P, a, b, s))) return st;
   Launcher L{ctx, s, false, {}, 0};
   if ((st = enqueue_dt(ctx, P, L, 1.0, dt, 0, nullptr))) return st;
+  if (axis == RIPPLE_FV_AXIS_XY) {
+    if (!P->fused)
+      return fail(ctx, RIPPLE_FV_E_UNSUPPORTED,
+                  "fused x-y sweep needs unlinked x and y faces, 16 <= n[0] <= 512 and split_xy = 0");
+    return enqueue_sweep_xy(ctx, P, L, 0, 1, false);
+  }
   return enqueue_sweep(ctx, P, L, axis, 0, 1, 0, false);
 }
 
-ripple_fv_status ripple_fv_step(ripple_fv_ctx* ctx, const ripple_fv_grid* g, void* u_in,
-                                void* u_out, double cfl, double dt, double* dt_dev,
+ripple_fv_status ripple_fv_step(ripple_fv_ctx* ctx, const ripple_fv_grid* g, void* u,
+                                void* work, double cfl, double dt, double* dt_dev,
                                 void* stream) {
   ripple_fv_status st = set_device(ctx);
   if (st) return st;
@@ -773,17 +856,17 @@ ripple_fv_status ripple_fv_step(ripple_fv_ctx* ctx, const ripple_fv_grid* g, voi
   if (dt_dev && (st = ptr_ok(ctx, dt_dev, 8, 8, "dt_dev"))) return st;
   ripple_fv_grid one = *g;
   one.group = -1;
-  void* a[1] = {u_in};
-  void* b[1] = {u_out};
+  void* a[1] = {u};
+  void* b[1] = {work};
   return run(ctx, 1, &one, a, b, 1, cfl, dt, dt_dev, 0, (hipStream_t)stream);
 }
 
 ripple_fv_status ripple_fv_run_batch(ripple_fv_ctx* ctx, int32_t n, const ripple_fv_grid* grids,
-                                     void* const* u_a, void* const* u_b, int32_t nsteps,
+                                     void* const* u, void* const* work, int32_t nsteps,
                                      double cfl, int32_t flags, void* stream) {
   ripple_fv_status st = set_device(ctx);
   if (st) return st;
-  return run(ctx, n, grids, u_a, u_b, nsteps, cfl, 0.0, nullptr, flags, (hipStream_t)stream);
+  return run(ctx, n, grids, u, work, nsteps, cfl, 0.0, nullptr, flags, (hipStream_t)stream);
 }
 
 ripple_fv_status ripple_fv_batch_time(ripple_fv_ctx* ctx, int32_t n, const ripple_fv_grid* grids,
@@ -804,8 +887,9 @@ ripple_fv_status ripple_fv_partition(const ripple_fv_grid* whole, const int32_t 
                                      int32_t first_index, ripple_fv_grid* sub) {
   if (!whole || !parts || !sub || first_index < 0) return RIPPLE_FV_E_INVALID;
   int64_t pitch[3], bytes;
+  int32_t ox;
   std::string why;
-  if (grid_check(whole, pitch, &bytes, &why)) return RIPPLE_FV_E_INVALID;
+  if (grid_check(whole, pitch, &bytes, &ox, &why)) return RIPPLE_FV_E_INVALID;
   for (int d = 0; d < 3; ++d)
     if (parts[d] < 1 || whole->n[d] / parts[d] < 2) return RIPPLE_FV_E_INVALID;
   for (int d = 0; d < 3; ++d)
@@ -966,7 +1050,7 @@ double time_candidate(ripple_fv_ctx* ctx, std::vector<ripple_fv_grid>& cand, dou
   hipEventCreate(&e0);
   hipEventCreate(&e1);
   hipEventRecord(e0, s);
-  *st = run(ctx, n, cand.data(), B.a.data(), B.b.data(), 3, 0.9, 0.0, nullptr, 0, s);
+  *st = run(ctx, n, cand.data(), B.a.data(), B.b.data(), 4, 0.9, 0.0, nullptr, 0, s);
   hipEventRecord(e1, s);
   hipEventSynchronize(e1);
   float ms = 0.f;
@@ -993,7 +1077,7 @@ extern "C" ripple_fv_status ripple_fv_batch_tune(ripple_fv_ctx* ctx, int32_t n,
   for (auto& g : base) {
     g.layout = RIPPLE_FV_SOA;
     g.aosoa_w = 0;
-    g.x_block = g.yz_block = g.yz_segment = g.persist = g.yz_cols = 0;
+    g.x_block = g.yz_block = g.yz_segment = g.persist = g.yz_cols = g.split_xy = 0;
     if (ripple_fv_grid_init(&g)) return fail(ctx, RIPPLE_FV_E_INVALID, "bad grid descriptor");
   }
   if ((st = validate_batch(ctx, n, base.data()))) return st;
@@ -1048,10 +1132,14 @@ extern "C" ripple_fv_status ripple_fv_batch_tune(ripple_fv_ctx* ctx, int32_t n,
       if (st) break;
       st = consider(with([&](ripple_fv_grid& g) { g.yz_block = yb; g.yz_segment = sg; }));
     }
-  // 4. x cells per y/z thread
+  // 4. x cells per y/z thread, fused or separate x and y sweeps
   for (int cols : {1, 2}) {
     if (st) break;
     st = consider(with([&](ripple_fv_grid& g) { g.yz_cols = cols; }));
+  }
+  for (int split : {0, 1}) {
+    if (st) break;
+    st = consider(with([&](ripple_fv_grid& g) { g.split_xy = split; }));
   }
   // 5. persistent launches
   for (int pc : {0, 2, 4, 8}) {

@@ -1,0 +1,68 @@
+// Index arithmetic of the sweeps that does not touch memory, kept apart so
+// that host code (and host-side checks) can evaluate exactly what the kernels
+// compute.
+#pragma once
+
+#include <stdint.h>
+
+#if defined(__HIPCC__)
+#include <hip/hip_runtime.h>
+#define RFV_HD __host__ __device__ __forceinline__
+#else
+#define RFV_HD inline
+#endif
+
+namespace rfv {
+
+enum FaceMode : int { FACE_TRANSMISSIVE = 0, FACE_PERIODIC = 1, FACE_HALO = 2 };
+
+// Interior index to load for position j (may lie in [-2, n+1]) along an axis:
+// transmissive faces clamp, periodic faces wrap, halo faces read the padding.
+RFV_HD int face_index(int j, int n, int mode_lo, int mode_hi) {
+  if (j < 0) return mode_lo == FACE_TRANSMISSIVE ? 0 : (mode_lo == FACE_PERIODIC ? j + n : j);
+  if (j >= n) return mode_hi == FACE_TRANSMISSIVE ? n - 1 : (mode_hi == FACE_PERIODIC ? j - n : j);
+  return j;
+}
+
+// Position of thread tid of an x-sweep chunk in the flattened (row, x) space of
+// a grid with row length lx = nx + 4 (padded x positions), ny rows per plane
+// and nz planes.  The chunk's first position F0 (= tile * chunk - 2, so -2 for
+// the first chunk) is decoded once per wave with one division; each lane then
+// walks forward from it, wrapping rows and planes, which costs a few
+// compares instead of three per-lane divisions.  Lanes past either end of the
+// space are marked invalid and clamped onto its first or last position so
+// that their loads stay in bounds.
+struct XPos {
+  int il;        // padded x index (0 .. lx-1) of the lane's position
+  int j0, k0;    // row and plane of the chunk's first in-range position (uniform)
+  int dj, dk;    // lane row/plane minus (j0, k0); dj may be negative after a plane wrap
+  bool valid;
+};
+
+RFV_HD XPos x_position(int tid, int F0, int lx, int ny, int nz) {
+  XPos r;
+  const int total = lx * ny * nz;
+  const int F0c = F0 < 0 ? 0 : F0;
+  const int row0 = F0c / lx;
+  const int il0 = F0c - row0 * lx;
+  r.j0 = row0 % ny;
+  r.k0 = row0 / ny;
+  const int f = F0 + tid;
+  r.valid = f >= 0 && f < total;
+  const int fc = f < 0 ? 0 : (f >= total ? total - 1 : f);
+  int il = il0 + (fc - F0c);
+  int j = r.j0, k = r.k0;
+  while (il >= lx) {
+    il -= lx;
+    if (++j == ny) {
+      j = 0;
+      ++k;
+    }
+  }
+  r.il = il;
+  r.dj = j - r.j0;
+  r.dk = k - r.k0;
+  return r;
+}
+
+}  // namespace rfv

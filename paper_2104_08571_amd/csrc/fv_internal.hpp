@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "fv_index.hpp"
 #include "ripple_fv.h"
 
 namespace rfv {
@@ -15,10 +16,6 @@ constexpr int HALO = RIPPLE_FV_HALO;
 enum Lay : int { LAY_AOS = 0, LAY_SOA = 1, LAY_AOSOA16 = 2, LAY_AOSOA32 = 3, LAY_AOSOA64 = 4,
                  LAY_COUNT = 5 };
 
-// Face treatment for a sweep: physical boundary condition or padding filled
-// from a neighbouring sub-block.
-enum FaceMode : int { FACE_TRANSMISSIVE = 0, FACE_PERIODIC = 1, FACE_HALO = 2 };
-
 // Device copy of one grid of a batch.  Read by every kernel through a
 // wave-uniform index, so the compiler keeps it in scalar registers.
 struct DevGrid {
@@ -26,10 +23,10 @@ struct DevGrid {
   int32_t n[3];        // interior extents
   int32_t mode[6];     // FaceMode per face (-x, +x, -y, +y, -z, +z)
   int64_t px, pxy;     // padded pitch of a row and of a plane, in cells
-  int64_t ptot;        // padded cells per buffer
+  int64_t ptot;        // cell slots per buffer (SoA component stride)
   double dx[3];
   int32_t group;       // index of the grid whose wave-speed slot and dt this grid uses
-  int32_t pad_;
+  int32_t ox;          // padded x index of interior x = 0
 };
 
 // Per-batch device workspace handed to the kernels.
@@ -73,6 +70,8 @@ struct Tiling {
   int yz_segment;  // cells per thread along y/z
   int persist;     // workgroups per CU for persistent launches, 0 = one per tile
   int yz_cols;     // adjacent x cells per thread in the y/z sweeps (1 or 2)
+  int split_xy;    // 1: separate x and y sweeps even where they could be fused
+  int xy_cols;     // adjacent x cells per thread in the fused x-y sweep (1 or 2)
 };
 
 int lay_of(const ripple_fv_grid& g);
@@ -81,12 +80,20 @@ int lay_of(const ripple_fv_grid& g);
 int64_t tiles_x(const ripple_fv_grid& g, int x_block);
 int64_t tiles_yz(const ripple_fv_grid& g, int axis, int yz_block, int yz_segment, int yz_cols);
 int64_t tiles_ws(const ripple_fv_grid& g);
+// Fused x-then-y sweep: workgroups of xy_threads(cols) lanes owning `cols`
+// adjacent x cells each, over whole x rows of nx >= XY_MIN_NX cells.
+constexpr int XY_MIN_NX = 16;
+constexpr int xy_threads(int cols) { return 512 / cols; }
+bool xy_eligible(const ripple_fv_grid& g, int cols);
+int64_t tiles_xy(const ripple_fv_grid& g, int yz_segment, int cols);
 constexpr int WS_BLOCK = 256;
 constexpr int WS_CELLS_PER_THREAD = 4;
 
 // Kernel launchers (return hipError_t of the launch).
 hipError_t launch_sweep(int dtype, int lay, int axis, const Tiling& tl, const SweepParams& p,
                         int grid_blocks, hipStream_t s);
+hipError_t launch_sweep_xy(int dtype, int lay, const Tiling& tl, const SweepParams& p,
+                           int grid_blocks, hipStream_t s);
 hipError_t launch_wavespeed(int dtype, int lay, const Work& w, int in, TileRange tr,
                             unsigned long long* s_out, int grid_blocks, hipStream_t s);
 hipError_t launch_dt(const Work& w, double cfl, double fixed_dt, int reset_s, double* dt_out,
@@ -102,7 +109,7 @@ struct Desc {
   int32_t n[3];
   int32_t lay;
   int32_t dtype;
-  int32_t pad_;
+  int32_t ox;          // padded x index of interior x = 0
   int64_t px, pxy, ptot;
 };
 hipError_t launch_import(const Desc& d, const double* src, int primitive, hipStream_t s);

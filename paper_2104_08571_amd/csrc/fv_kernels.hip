@@ -23,6 +23,7 @@
 #include <hip/hip_runtime.h>
 
 #include "fv_internal.hpp"
+#include "fv_index.hpp"
 #include "fv_layout.hpp"
 #include "fv_math.hpp"
 
@@ -50,13 +51,6 @@ __device__ __forceinline__ int find_grid(const int64_t* start, int n, int64_t t)
   return uniform(lo);
 }
 
-// Interior index to load for position j (may lie in [-2, n+1]) along an axis:
-// transmissive faces clamp, periodic faces wrap, halo faces read the padding.
-__device__ __forceinline__ int face_index(int j, int n, int mode_lo, int mode_hi) {
-  if (j < 0) return mode_lo == FACE_TRANSMISSIVE ? 0 : (mode_lo == FACE_PERIODIC ? j + n : j);
-  if (j >= n) return mode_hi == FACE_TRANSMISSIVE ? n - 1 : (mode_hi == FACE_PERIODIC ? j - n : j);
-  return j;
-}
 
 // Maximum of two non-negative values by their bit patterns (they order like
 // unsigned integers); a NaN pattern exceeds every finite one, so it wins.
@@ -104,6 +98,7 @@ __device__ __forceinline__ void fold_wavespeeds(T s[3], bool bad, unsigned long 
 // x sweep
 // ---------------------------------------------------------------------------
 
+
 // Chunk of NT consecutive positions of the flattened (row, x) space, rows
 // being the interior (j, k) pairs and positions within a row running over
 // x = -2 .. n0+1 (the padded columns).  Thread t holds position
@@ -121,26 +116,19 @@ __global__ void __launch_bounds__(NT) k_sweep_x(SweepParams p, const DevGrid* __
     const int64_t gt = uniform(p.tiles.first + b);
     const int g = find_grid(tile_start, p.w.ngrids, gt);
     const DevGrid& G = grids[g];
-    const int64_t lt = gt - tile_start[g];
+    const int lt = (int)(gt - tile_start[g]);
     const int nx = G.n[0], ny = G.n[1];
-    const uint32_t lx = (uint32_t)(nx + 4);
-    const int64_t total = (int64_t)lx * ny * G.n[2];
-    const int64_t f = lt * C - 2 + tid;
-    const bool valid = f >= 0 && f < total;
-    const uint32_t fc = (uint32_t)(f < 0 ? 0 : (f >= total ? total - 1 : f));
-    const uint32_t row = fc / lx;
-    const int il = (int)(fc - row * lx);             // padded x index
-    const int j = (int)(row % (uint32_t)ny);
-    const int k = (int)(row / (uint32_t)ny);
-    const int i = face_index(il - 2, nx, G.mode[0], G.mode[1]);
-    const int64_t rowq = (int64_t)(k + 2) * G.pxy + (int64_t)(j + 2) * G.px;
+    const XPos xp = x_position(tid, lt * C - 2, nx + 4, ny, G.n[2]);
+    const int i = face_index(xp.il - 2, nx, G.mode[0], G.mode[1]);
     // uniform base: the chunk's first row, aligned down to 64 cells
-    const uint32_t fu = (uint32_t)(lt * C < 2 ? 0 : lt * C - 2);
-    const uint32_t row0 = fu / lx;
-    const int64_t q0 = uniform(((int64_t)(row0 / (uint32_t)ny + 2) * G.pxy +
-                                (int64_t)(row0 % (uint32_t)ny + 2) * G.px) & ~int64_t(63));
-    const uint32_t lane_ld = Layout<LAY>::rel((uint32_t)(rowq + i + 2 - q0)) * (uint32_t)sizeof(T);
-    const uint32_t lane_st = Layout<LAY>::rel((uint32_t)(rowq + il - q0)) * (uint32_t)sizeof(T);
+    const int64_t qrow0 = (int64_t)(xp.k0 + 2) * G.pxy + (int64_t)(xp.j0 + 2) * G.px;
+    const int64_t q0 = uniform(qrow0 & ~int64_t(63));
+    const uint32_t rowoff = (uint32_t)(qrow0 - q0) + (uint32_t)xp.dk * (uint32_t)G.pxy +
+                            (uint32_t)xp.dj * (uint32_t)G.px;
+    const bool valid = xp.valid;
+    const int il = xp.il;
+    const uint32_t lane_ld = Layout<LAY>::rel(rowoff + (uint32_t)(i + G.ox)) * (uint32_t)sizeof(T);
+    const uint32_t lane_st = Layout<LAY>::rel(rowoff + (uint32_t)(il - 2 + G.ox)) * (uint32_t)sizeof(T);
     const T lam = (T)lamv[g * 3 + 0];
     const T hl = T(0.5) * lam;
 
@@ -244,8 +232,8 @@ __global__ void __launch_bounds__(256) k_sweep_yz(SweepParams p, const DevGrid* 
     for (int k = 0; k < COLS; ++k) act[k] = active && ia + k < na;
     const int64_t across = D == 1 ? G.pxy : G.px;
     const int64_t stride = D == 1 ? G.px : G.pxy;
-    const int64_t qlane = (int64_t)(ia + 2) + (int64_t)(ib + 2) * across;
-    const int64_t qfirst = (int64_t)(ia0 + 2) + (int64_t)(ib0 + 2) * across;
+    const int64_t qlane = (int64_t)(ia + G.ox) + (int64_t)(ib + 2) * across;
+    const int64_t qfirst = (int64_t)(ia0 + G.ox) + (int64_t)(ib0 + 2) * across;
     const int64_t q0 = uniform(qfirst & ~int64_t(63));
     const uint32_t lane = Layout<LAY>::rel((uint32_t)(qlane - q0)) * (uint32_t)sizeof(T);
     const int mlo = G.mode[2 * D], mhi = G.mode[2 * D + 1];
@@ -344,6 +332,284 @@ __global__ void __launch_bounds__(256) k_sweep_yz(SweepParams p, const DevGrid* 
 }
 
 // ---------------------------------------------------------------------------
+// Fused x-then-y sweep
+// ---------------------------------------------------------------------------
+
+// The y sweep of cell (i, j, k) reads the x-swept states of column (i, k) at
+// rows j-2 .. j+2 only, and the x sweep of a row needs nothing but that row.
+// So a workgroup that owns whole x rows of a few z planes can march along y,
+// x-sweep each row it loads (neighbours exchanged through LDS) and feed the
+// result straight into the y sweep's register window: the state is read and
+// written once for both sweeps.  Each cell undergoes exactly the arithmetic
+// of k_sweep_x followed by k_sweep_yz along y, so the result is bitwise that
+// of the two separate kernels.
+//
+// Tile = (R whole x rows at consecutive z, R = NT / groups per row) x
+// (segment of p.seg rows along y).  Lane t owns the CX cells i0 .. i0+CX-1 of
+// row slot t / groups.  Per loaded row: publish the cells (and the x ghost
+// cells the boundary condition defines) to LDS; reconstruct own cells and
+// publish the right evolved state of the last one; compute the left face flux
+// of each own cell and publish the first; update.  The x ghost reconstruction
+// and the right-most face come from the periodic partner cell, or are
+// computed by the edge lane for transmissive faces.  Faces linked to other
+// sub-blocks (halo padding) are not handled here: such grids use the
+// separate kernels.
+//
+// Rings (period 3): raw rows are loaded three iterations before they are
+// x-swept; x-swept rows j, j+1, j+2 are held while cell j is updated.
+template <typename T, int LAY, int CX, int NT>
+__global__ void __launch_bounds__(NT) k_sweep_xy(SweepParams p, const DevGrid* __restrict__ grids,
+                                                 const int64_t* __restrict__ tile_start,
+                                                 const double* __restrict__ lamv) {
+  // LDS slots per component: R rows of nx + 4 with nx >= XY_MIN_NX
+  constexpr int LN = NT * CX + 4 * (NT * CX / XY_MIN_NX);
+  __shared__ T sU[5][LN];
+  __shared__ T sR[5][LN];
+  __shared__ T sF[5][LN];
+  const int tid = threadIdx.x;
+  for (int64_t b = xcd_order(blockIdx.x, gridDim.x); b < p.tiles.count; b += gridDim.x) {
+    const int64_t gt = uniform(p.tiles.first + b);
+    const int g = find_grid(tile_start, p.w.ngrids, gt);
+    const DevGrid& G = grids[g];
+    const int lt = (int)(gt - tile_start[g]);
+    const int nx = G.n[0], ny = G.n[1], nz = G.n[2];
+    const int npr = (nx + CX - 1) / CX;           // lane groups per row
+    const int R = NT / npr;                        // rows per tile
+    const int nseg = (ny + p.seg - 1) / p.seg;
+    const int chunk = lt / nseg;
+    const int s = lt - chunk * nseg;
+    const int rs = tid / npr;                      // row slot of this lane
+    const int i0 = (tid - rs * npr) * CX;
+    const int kk = chunk * R + rs;
+    const bool on = rs < R && kk < nz;             // the lane owns cells
+    bool has[CX];
+#pragma unroll
+    for (int m = 0; m < CX; ++m) has[m] = on && i0 + m < nx;
+    const int nlast = min(CX, nx - i0);            // cells the lane owns (if on)
+    const bool periodic_x = G.mode[0] == FACE_PERIODIC;
+    const int LP = nx + 4;                         // LDS row pitch
+    const int lb = (on ? rs : 0) * LP + 2;         // LDS slot of cell 0 of the lane's row
+    // addresses: column (i0, kk) at row j is q0 + (j + 2) Px + lane offset
+    const int kc = on ? kk : chunk * R;
+    const int ic = on ? i0 : 0;
+    const int64_t qlane = (int64_t)(kc + 2) * G.pxy + (ic + G.ox);
+    const int64_t q0 = uniform(((int64_t)(chunk * R + 2) * G.pxy + G.ox) & ~int64_t(63));
+    const uint32_t lane = Layout<LAY>::rel((uint32_t)(qlane - q0)) * (uint32_t)sizeof(T);
+    const int mlo = G.mode[2], mhi = G.mode[3];
+    const void* src = G.buf[p.in];
+    void* dst = G.buf[p.out];
+    const T lamx = (T)lamv[g * 3 + 0];
+    const T hlx = T(0.5) * lamx;
+    const T lamy = (T)lamv[g * 3 + 1];
+    const T hly = T(0.5) * lamy;
+    const int j0 = s * p.seg;
+    const int len = min(p.seg, ny - j0);
+    const int jlast = j0 + len + 1;
+    const int64_t ptot = G.ptot;
+
+    auto row = [&](int j) -> int64_t {
+      return q0 + (int64_t)(face_index(min(j, jlast), ny, mlo, mhi) + 2) * G.px;
+    };
+
+    // x sweep of one row held by the lanes: u (inputs) -> o (x-swept)
+    auto xsweep = [&](const T u[CX][5], T o[CX][5]) __attribute__((always_inline)) {
+#pragma unroll
+      for (int m = 0; m < CX; ++m) {
+        if (has[m]) {
+          const int i = i0 + m;
+#pragma unroll
+          for (int c = 0; c < 5; ++c) sU[c][lb + i] = u[m][c];
+          if (periodic_x) {
+            if (i >= nx - 2) {
+#pragma unroll
+              for (int c = 0; c < 5; ++c) sU[c][lb + i - nx] = u[m][c];
+            }
+            if (i < 2) {
+#pragma unroll
+              for (int c = 0; c < 5; ++c) sU[c][lb + nx + i] = u[m][c];
+            }
+          } else {
+            if (i == 0) {
+#pragma unroll
+              for (int c = 0; c < 5; ++c) sU[c][lb - 1] = sU[c][lb - 2] = u[m][c];
+            }
+            if (i == nx - 1) {
+#pragma unroll
+              for (int c = 0; c < 5; ++c) sU[c][lb + nx] = sU[c][lb + nx + 1] = u[m][c];
+            }
+          }
+        }
+      }
+      __syncthreads();
+      T bl[CX][5], br[CX][5];
+#pragma unroll
+      for (int m = 0; m < CX; ++m) {
+        T dm[5], dp[5];
+        const int i = i0 + m;
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+          const T um = m > 0 ? u[m - 1][c] : sU[c][lb + i - 1];
+          const T up = (m + 1 < CX && m + 1 < nlast) ? u[m + 1][c] : sU[c][lb + i + 1];
+          dm[c] = u[m][c] - um;
+          dp[c] = up - u[m][c];
+        }
+        hancock<T, 0>(u[m], dm, dp, hlx, bl[m], br[m]);
+      }
+      if (on) {
+        const int ml = nlast - 1;
+#pragma unroll
+        for (int m = 0; m < CX; ++m) {
+          if (m == ml) {
+#pragma unroll
+            for (int c = 0; c < 5; ++c) sR[c][lb + i0 + m] = br[m][c];
+            if (periodic_x && i0 + m == nx - 1) {
+#pragma unroll
+              for (int c = 0; c < 5; ++c) sR[c][lb - 1] = br[m][c];
+            }
+          }
+        }
+        if (!periodic_x && i0 == 0) {
+          // ghost cell -1: stencil u_{-2}, u_{-1}, u_0
+          T ug[5], dm[5], dp[5], gl[5], gr[5];
+#pragma unroll
+          for (int c = 0; c < 5; ++c) {
+            ug[c] = sU[c][lb - 1];
+            dm[c] = ug[c] - sU[c][lb - 2];
+            dp[c] = u[0][c] - ug[c];
+          }
+          hancock<T, 0>(ug, dm, dp, hlx, gl, gr);
+#pragma unroll
+          for (int c = 0; c < 5; ++c) sR[c][lb - 1] = gr[c];
+        }
+      }
+      __syncthreads();
+      T fl[CX][5];
+#pragma unroll
+      for (int m = 0; m < CX; ++m) {
+        T left[5];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) left[c] = m > 0 ? br[m - 1][c] : sR[c][lb + i0 - 1];
+        hllc<T, 0>(left, bl[m], fl[m]);                 // face i0 + m - 1/2
+      }
+      if (on) {
+#pragma unroll
+        for (int c = 0; c < 5; ++c) sF[c][lb + i0] = fl[0][c];
+        if (periodic_x) {
+          if (i0 == 0) {
+#pragma unroll
+            for (int c = 0; c < 5; ++c) sF[c][lb + nx] = fl[0][c];
+          }
+        } else if (i0 + nlast == nx) {
+          // ghost cell nx: stencil u_{nx-1}, u_nx, u_{nx+1}; face nx - 1/2
+          const int ml = nlast - 1;
+          T ue[5], ug[5], dm[5], dp[5], gl[5], gr[5], fg[5];
+#pragma unroll
+          for (int m = 0; m < CX; ++m) {
+            if (m == ml) {
+#pragma unroll
+              for (int c = 0; c < 5; ++c) ue[c] = br[m][c];
+#pragma unroll
+              for (int c = 0; c < 5; ++c) {
+                ug[c] = sU[c][lb + nx];
+                dm[c] = ug[c] - u[m][c];
+                dp[c] = sU[c][lb + nx + 1] - ug[c];
+              }
+            }
+          }
+          hancock<T, 0>(ug, dm, dp, hlx, gl, gr);
+          hllc<T, 0>(ue, gl, fg);
+#pragma unroll
+          for (int c = 0; c < 5; ++c) sF[c][lb + nx] = fg[c];
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int m = 0; m < CX; ++m) {
+        T fp[5];
+#pragma unroll
+        for (int c = 0; c < 5; ++c)
+          fp[c] = (m + 1 < CX && m + 1 < nlast) ? fl[m + 1][c] : sF[c][lb + i0 + m + 1];
+        update(u[m], lamx, fp, fl[m], o[m]);
+      }
+    };
+
+    // raw ring slot of row r and x-swept ring slot: (r - (j0 - 2)) mod 3
+    T raw[3][CX][5];
+    T xs[3][CX][5];
+    T dprev[CX][5], dnext[5], bl[5], br[CX][5], brp[CX][5], fprev[CX][5];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) load_group<T, LAY, CX>(src, row(j0 - 2 + k), ptot, lane, raw[k]);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      xsweep(raw[k], xs[k]);                                      // rows j0-2, j0-1, j0
+      load_group<T, LAY, CX>(src, row(j0 + 1 + k), ptot, lane, raw[k]);
+    }
+#pragma unroll
+    for (int m = 0; m < CX; ++m) {
+#pragma unroll
+      for (int c = 0; c < 5; ++c) {
+        dprev[m][c] = xs[1][m][c] - xs[0][m][c];
+        dnext[c] = xs[2][m][c] - xs[1][m][c];
+      }
+      hancock<T, 1>(xs[1][m], dprev[m], dnext, hly, bl, brp[m]);   // cell j0 - 1
+#pragma unroll
+      for (int c = 0; c < 5; ++c) dprev[m][c] = dnext[c];
+    }
+    xsweep(raw[0], xs[0]);                                          // row j0 + 1
+    load_group<T, LAY, CX>(src, row(j0 + 4), ptot, lane, raw[0]);
+#pragma unroll
+    for (int m = 0; m < CX; ++m) {
+#pragma unroll
+      for (int c = 0; c < 5; ++c) dnext[c] = xs[0][m][c] - xs[2][m][c];
+      hancock<T, 1>(xs[2][m], dprev[m], dnext, hly, bl, br[m]);    // cell j0
+      hllc<T, 1>(brp[m], bl, fprev[m]);                            // face j0 - 1/2
+#pragma unroll
+      for (int c = 0; c < 5; ++c) {
+        brp[m][c] = br[m][c];
+        dprev[m][c] = dnext[c];
+      }
+    }
+
+    // Iteration o (cell j = j0 + o), k = o mod 3: xs[(k+2)%3] = U_j,
+    // xs[k] = U_{j+1}; row j+2 is x-swept from raw[(k+1)%3] into
+    // xs[(k+1)%3] (the slot of U_{j-1}), and row j+5 is loaded into the raw
+    // slot just consumed.  dprev = U_{j+1} - U_j, brp = Ub^R_j, fprev = F_{j-1/2}.
+    for (int o0 = 0; o0 < len; o0 += 3) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const int o = o0 + k;
+        if (o >= len) break;
+        const int j = j0 + o;
+        xsweep(raw[(k + 1) % 3], xs[(k + 1) % 3]);                 // row j + 2
+        load_group<T, LAY, CX>(src, row(j + 5), ptot, lane, raw[(k + 1) % 3]);
+        T out[CX][5];
+#pragma unroll
+        for (int m = 0; m < CX; ++m) {
+          const T* uj = xs[(k + 2) % 3][m];
+          const T* uj1 = xs[k][m];
+          const T* uj2 = xs[(k + 1) % 3][m];
+#pragma unroll
+          for (int c = 0; c < 5; ++c) dnext[c] = uj2[c] - uj1[c];
+          hancock<T, 1>(uj1, dprev[m], dnext, hly, bl, br[m]);     // cell j + 1
+          T fcur[5];
+          hllc<T, 1>(brp[m], bl, fcur);                            // face j + 1/2
+          update(uj, lamy, fcur, fprev[m], out[m]);
+#pragma unroll
+          for (int c = 0; c < 5; ++c) {
+            fprev[m][c] = fcur[c];
+            brp[m][c] = br[m][c];
+            dprev[m][c] = dnext[c];
+          }
+        }
+        if (has[0])
+          store_group<T, LAY, CX>(dst, q0 + (int64_t)(j + 2) * G.px, ptot, lane, out, has[CX - 1]);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Wave speeds, time step, halo copies, fills
 // ---------------------------------------------------------------------------
 
@@ -369,7 +635,7 @@ __global__ void __launch_bounds__(WS_BLOCK) k_wavespeed(Work w, int in, TileRang
         const uint32_t fu = (uint32_t)f;
         const uint32_t row = fu / nx;
         const uint32_t i = fu - row * nx, jj = row % ny, kk = row / ny;
-        const int64_t q = (int64_t)(kk + 2) * G.pxy + (int64_t)(jj + 2) * G.px + (i + 2);
+        const int64_t q = (int64_t)(kk + 2) * G.pxy + (int64_t)(jj + 2) * G.px + (i + G.ox);
         T u[5], s[3];
         bool b_;
         load_cell<T, LAY>(G.buf[in], q, G.ptot, u);
@@ -438,15 +704,18 @@ __global__ void __launch_bounds__(256) k_halo(Work w, int buf, int axis, const H
   const int64_t s_ax = axis == 0 ? 1 : (axis == 1 ? Gs.px : Gs.pxy);
   const int nd = axis == 0 ? Gd.n[0] : (axis == 1 ? Gd.n[1] : Gd.n[2]);
   const int ns = axis == 0 ? Gs.n[0] : (axis == 1 ? Gs.n[1] : Gs.n[2]);
+  // padded index origin along the copy axis and along the first axis across
+  const int d_o = axis == 0 ? Gd.ox : 2, s_o = axis == 0 ? Gs.ox : 2;
+  const int d_o0 = a0 == 0 ? Gd.ox : 2, s_o0 = a0 == 0 ? Gs.ox : 2;
   for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < 2 * area;
        e += gridDim.x * blockDim.x) {
     const uint32_t layer = e / area, r = e - layer * area;
     const uint32_t ia = r % na, ib = r / na;
-    // padded index along the axis: destination padding, source interior edge
-    const int dpos = tk.side == 0 ? (int)layer : nd + 2 + (int)layer;
-    const int spos = tk.side == 0 ? ns + (int)layer : 2 + (int)layer;
-    const int64_t across_d = (int64_t)(ia + 2) * d_a0 + (int64_t)(ib + 2) * d_a1;
-    const int64_t across_s = (int64_t)(ia + 2) * s_a0 + (int64_t)(ib + 2) * s_a1;
+    // index along the axis: destination padding, source interior edge
+    const int dpos = (tk.side == 0 ? (int)layer - 2 : nd + (int)layer) + d_o;
+    const int spos = (tk.side == 0 ? ns - 2 + (int)layer : (int)layer) + s_o;
+    const int64_t across_d = (int64_t)(ia + d_o0) * d_a0 + (int64_t)(ib + 2) * d_a1;
+    const int64_t across_s = (int64_t)(ia + s_o0) * s_a0 + (int64_t)(ib + 2) * s_a1;
     T u[5];
     load_cell<T, LAY>(Gs.buf[buf], across_s + spos * s_ax, Gs.ptot, u);
     store_cell<T, LAY>(Gd.buf[buf], across_d + dpos * d_ax, Gd.ptot, u);
@@ -472,7 +741,7 @@ __global__ void k_fill_f64(double* p, int64_t n, double v) {
 __device__ __forceinline__ int64_t desc_q(const Desc& d, int64_t f) {
   const int64_t nx = d.n[0], ny = d.n[1];
   const int64_t i = f % nx, row = f / nx, j = row % ny, k = row / ny;
-  return (k + 2) * d.pxy + (j + 2) * d.px + (i + 2);
+  return (k + 2) * d.pxy + (j + 2) * d.px + (i + d.ox);
 }
 
 __device__ __forceinline__ double load_rt(const Desc& d, int64_t q, int c) {
@@ -639,6 +908,18 @@ int64_t tiles_yz(const ripple_fv_grid& g, int axis, int yz_block, int yz_segment
   return nchunk * nseg;
 }
 
+bool xy_eligible(const ripple_fv_grid& g, int cols) {
+  return g.n[0] >= XY_MIN_NX && (g.n[0] + cols - 1) / cols <= xy_threads(cols) && g.nbr[0] < 0 &&
+         g.nbr[1] < 0 && g.nbr[2] < 0 && g.nbr[3] < 0;
+}
+
+int64_t tiles_xy(const ripple_fv_grid& g, int yz_segment, int cols) {
+  const int64_t rows = xy_threads(cols) / ((g.n[0] + cols - 1) / cols);
+  const int64_t nchunk = (g.n[2] + rows - 1) / rows;
+  const int64_t nseg = (g.n[1] + yz_segment - 1) / yz_segment;
+  return nchunk * nseg;
+}
+
 int64_t tiles_ws(const ripple_fv_grid& g) {
   const int64_t ncell = (int64_t)g.n[0] * g.n[1] * g.n[2];
   const int64_t per = WS_BLOCK * WS_CELLS_PER_THREAD;
@@ -696,6 +977,37 @@ hipError_t launch_sweep(int dtype, int lay, int axis, const Tiling& tl, const Sw
   if (p.tiles.count <= 0) return hipSuccess;
   return dtype == RIPPLE_FV_F32 ? sweep_lay<float>(lay, axis, tl, p, grid_blocks, s)
                                 : sweep_lay<double>(lay, axis, tl, p, grid_blocks, s);
+}
+
+template <typename T, int LAY>
+static hipError_t sweep_xy_typed(const Tiling& tl, const SweepParams& p, int blocks, hipStream_t s) {
+  const DevGrid* G = p.w.grids;
+  const int64_t* TS = p.tiles.tile_start;
+  const double* L = p.w.lam;
+  if (tl.yz_cols == 2)
+    hipLaunchKernelGGL((k_sweep_xy<T, LAY, 2, xy_threads(2)>), dim3(blocks), dim3(xy_threads(2)), 0, s, p, G, TS, L);
+  else
+    hipLaunchKernelGGL((k_sweep_xy<T, LAY, 1, xy_threads(1)>), dim3(blocks), dim3(xy_threads(1)), 0, s, p, G, TS, L);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t sweep_xy_lay(int lay, const Tiling& tl, const SweepParams& p, int blocks,
+                               hipStream_t s) {
+  switch (lay) {
+    case LAY_AOS: return sweep_xy_typed<T, LAY_AOS>(tl, p, blocks, s);
+    case LAY_SOA: return sweep_xy_typed<T, LAY_SOA>(tl, p, blocks, s);
+    case LAY_AOSOA16: return sweep_xy_typed<T, LAY_AOSOA16>(tl, p, blocks, s);
+    case LAY_AOSOA32: return sweep_xy_typed<T, LAY_AOSOA32>(tl, p, blocks, s);
+    default: return sweep_xy_typed<T, LAY_AOSOA64>(tl, p, blocks, s);
+  }
+}
+
+hipError_t launch_sweep_xy(int dtype, int lay, const Tiling& tl, const SweepParams& p,
+                           int grid_blocks, hipStream_t s) {
+  if (p.tiles.count <= 0) return hipSuccess;
+  return dtype == RIPPLE_FV_F32 ? sweep_xy_lay<float>(lay, tl, p, grid_blocks, s)
+                                : sweep_xy_lay<double>(lay, tl, p, grid_blocks, s);
 }
 
 template <typename T>

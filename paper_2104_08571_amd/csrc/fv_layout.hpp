@@ -1,7 +1,8 @@
 // Address maps of the three cell layouts (the paper's polymorphic data layout,
 // section "Polymorphic Data Layout", plus a blocked AoSoA variant).
 //
-// q is the padded linear cell index (k Py + j) Px + i; ptot = Px Py Pz.
+// q is the padded linear cell index ((k + 2) Py + j + 2) Px + i + ox of cell
+// (i, j, k); ptot is the number of cell slots per buffer.
 //   AoS      q * 5 + c                        (contiguous cell)
 //   SoA      c * ptot + q                     (strided components)
 //   AoSoA<W> ((q / W) * 5 + c) * W + q % W    (W consecutive cells per component block)

@@ -21,8 +21,9 @@ F32, F64 = 0, 1
 TRANSMISSIVE, PERIODIC = 0, 1
 PRIMITIVE, CONSERVED = 0, 1
 RUN_EAGER, RUN_GRAPH, RUN_PER_GRID, RUN_PROFILE = 0, 1, 2, 4
-K_WAVESPEED, K_DT, K_SWEEP_X, K_SWEEP_Y, K_SWEEP_Z, K_HALO, NKERNELS = range(7)
-KERNEL_NAMES = ["wavespeed", "dt", "sweep_x", "sweep_y", "sweep_z", "halo"]
+K_WAVESPEED, K_DT, K_SWEEP_X, K_SWEEP_Y, K_SWEEP_Z, K_HALO, K_SWEEP_XY, NKERNELS = range(8)
+KERNEL_NAMES = ["wavespeed", "dt", "sweep_x", "sweep_y", "sweep_z", "halo", "sweep_xy"]
+AXIS_XY = 3
 HALO = 2
 NVAR = 5
 
@@ -52,7 +53,9 @@ class Grid(ctypes.Structure):
         ("yz_segment", ctypes.c_int32),
         ("persist", ctypes.c_int32),
         ("yz_cols", ctypes.c_int32),
+        ("split_xy", ctypes.c_int32),
         ("reserved", ctypes.c_int32),
+        ("x_origin", ctypes.c_int32),
         ("pitch", ctypes.c_int64 * 3),
         ("bytes", ctypes.c_int64),
     ]
@@ -61,7 +64,8 @@ class Grid(ctypes.Structure):
         return (f"Grid(n={list(self.n)}, bc={list(self.bc)}, layout={self.layout}, "
                 f"dtype={self.dtype}, aosoa_w={self.aosoa_w}, group={self.group}, "
                 f"nbr={list(self.nbr)}, tiling=({self.x_block}, {self.yz_block}, "
-                f"{self.yz_segment}, {self.persist}, {self.yz_cols}), bytes={self.bytes})")
+                f"{self.yz_segment}, {self.persist}, {self.yz_cols}), split_xy={self.split_xy}, "
+                f"bytes={self.bytes})")
 
 
 class RippleFVError(RuntimeError):
@@ -181,14 +185,14 @@ def ripple_fv_sweep(ctx, g, axis, u_in, u_out, dt, stream=None):
     _check(lib().ripple_fv_sweep(ctx, ctypes.byref(g), axis, u_in, u_out, float(dt), stream), ctx)
 
 
-def ripple_fv_step(ctx, g, u_in, u_out, cfl=0.9, dt=0.0, dt_dev=None, stream=None):
-    _check(lib().ripple_fv_step(ctx, ctypes.byref(g), u_in, u_out, float(cfl), float(dt),
+def ripple_fv_step(ctx, g, u, work, cfl=0.9, dt=0.0, dt_dev=None, stream=None):
+    _check(lib().ripple_fv_step(ctx, ctypes.byref(g), u, work, float(cfl), float(dt),
                                 dt_dev, stream), ctx)
 
 
-def ripple_fv_run_batch(ctx, grids, u_a, u_b, nsteps, cfl=0.9, flags=RUN_EAGER, stream=None):
+def ripple_fv_run_batch(ctx, grids, u, work, nsteps, cfl=0.9, flags=RUN_EAGER, stream=None):
     arr, n = _grids(grids)
-    _check(lib().ripple_fv_run_batch(ctx, n, arr, _ptrs(u_a), _ptrs(u_b), int(nsteps),
+    _check(lib().ripple_fv_run_batch(ctx, n, arr, _ptrs(u), _ptrs(work), int(nsteps),
                                      float(cfl), int(flags), stream), ctx)
 
 
@@ -261,8 +265,9 @@ def call(name, *args):
 # -- descriptor helper ----------------------------------------------------------
 
 def make_grid(n, dtype=F64, layout=SOA, bc=(TRANSMISSIVE,) * 3, dx=None, aosoa_w=0,
-              group=-1, nbr=(-1,) * 6, tiling=(0, 0, 0, 0, 0)):
-    """A ripple_fv_grid with pitch and bytes filled (ripple_fv_grid_init)."""
+              group=-1, nbr=(-1,) * 6, tiling=(0, 0, 0, 0, 0, 0)):
+    """A ripple_fv_grid with pitch and bytes filled (ripple_fv_grid_init).
+    tiling = (x_block, yz_block, yz_segment, persist, yz_cols, split_xy)."""
     g = Grid()
     n = [int(v) for v in n]
     for d in range(3):
@@ -275,8 +280,9 @@ def make_grid(n, dtype=F64, layout=SOA, bc=(TRANSMISSIVE,) * 3, dx=None, aosoa_w
     g.dtype = int(dtype)
     g.aosoa_w = int(aosoa_w)
     g.group = int(group)
-    tiling = list(tiling) + [0] * (5 - len(tiling))
-    g.x_block, g.yz_block, g.yz_segment, g.persist, g.yz_cols = [int(v) for v in tiling]
+    tiling = list(tiling) + [0] * (6 - len(tiling))
+    (g.x_block, g.yz_block, g.yz_segment, g.persist, g.yz_cols,
+     g.split_xy) = [int(v) for v in tiling]
     return ripple_fv_grid_init(g)
 
 

@@ -49,7 +49,8 @@ def export(g, buf):
 
 def run(grids, states, nsteps, cfl=0.9, flags=R.RUN_EAGER):
     """Run a batch from primitive initial states; returns (list of FP64
-    conserved arrays, list of times)."""
+    conserved arrays, list of times).  The state advances in place in the
+    first buffer; the second is workspace."""
     if isinstance(grids, R.Grid):
         grids = [grids]
         states = [states]
@@ -60,8 +61,7 @@ def run(grids, states, nsteps, cfl=0.9, flags=R.RUN_EAGER):
     torch.cuda.synchronize()
     assert R.ripple_fv_check(ctx()) == R.OK
     t, _ = R.ripple_fv_batch_time(ctx(), grids)
-    res = b if nsteps % 2 == 1 else a
-    return [export(g, x) for g, x in zip(grids, res)], t
+    return [export(g, x) for g, x in zip(grids, a)], t
 
 
 def rel_l1(a, b):
@@ -83,6 +83,21 @@ def assert_parity(gpu, ref, tol, what=""):
 
 def unit_dx(n):
     return [1.0 / n[0], 1.0 / n[1], 1.0 / n[2]]
+
+
+def padded_cells(g, buf):
+    """The buffer as an FP64 array [5, nz+4, ny+4, nx+4] over the cells
+    (i, j, k) in [-2, n+2)^3, interior plus padding (SoA only)."""
+    assert g.layout == R.SOA
+    px, py, _ = g.pitch
+    slots = g.bytes // (5 * (4 if g.dtype == R.F32 else 8))
+    flat = (buf.view(torch.float32) if g.dtype == R.F32 else buf.view(torch.float64))
+    flat = flat.reshape(5, slots).cpu().numpy().astype(np.float64)
+    i = np.arange(-2, g.n[0] + 2)[None, None, :]
+    j = np.arange(-2, g.n[1] + 2)[None, :, None]
+    k = np.arange(-2, g.n[2] + 2)[:, None, None]
+    q = ((k + 2) * py + (j + 2)) * px + i + g.x_origin
+    return flat[:, q]
 
 
 class RawDeviceBuffer:

@@ -30,21 +30,49 @@ def test_library_exports_every_symbol():
 
 
 def test_grid_struct_size():
-    # 3*4 + 3*4 + 3*8 + 4*4 + 6*4 + 6*4 + 3*8 + 8, no padding holes
-    assert ctypes.sizeof(R.Grid) == 144
+    # 3*4 + 3*4 + 3*8 + 4*4 + 6*4 + 8*4 + 3*8 + 8, no padding holes
+    assert ctypes.sizeof(R.Grid) == 152
+    assert R.Grid.pitch.offset == 120
+
+
+def slots(px, py, pz, ox):
+    return (px * py * pz + ox + 63) // 64 * 64
 
 
 def test_grid_init_pitches():
+    # SoA: interior rows start on 128-byte lines (x_origin = 128 B / element)
     g = R.make_grid((10, 7, 5), dtype=R.F32, layout=R.SOA)
-    assert list(g.pitch) == [14, 11, 9]
-    assert g.bytes == 14 * 11 * 9 * 5 * 4
+    assert list(g.pitch) == [32, 11, 9] and g.x_origin == 32
+    assert g.bytes == slots(32, 11, 9, 32) * 5 * 4
+    g = R.make_grid((512, 7, 5), dtype=R.F32, layout=R.SOA)
+    assert g.pitch[0] == 544
+    g = R.make_grid((512, 7, 5), dtype=R.F64, layout=R.SOA)
+    assert list(g.pitch) == [528, 11, 9] and g.x_origin == 16
+    # AoS: row pitch rounded up to even, interior at x index 2
     g = R.make_grid((11, 7, 5), dtype=R.F32, layout=R.AOS)
-    assert list(g.pitch) == [16, 11, 9]  # row pitch rounded up to even
+    assert list(g.pitch) == [16, 11, 9] and g.x_origin == 2
+    assert g.bytes == slots(16, 11, 9, 2) * 5 * 4
+    # AoSoA: rows start on a block and on a 128-byte line
     g = R.make_grid((10, 7, 5), dtype=R.F64, layout=R.AOSOA, aosoa_w=16)
-    assert list(g.pitch) == [16, 11, 9]
-    assert g.bytes == 16 * 11 * 9 * 5 * 8
+    assert list(g.pitch) == [16, 11, 9] and g.x_origin == 16
+    assert g.bytes == slots(16, 11, 9, 16) * 5 * 8
     g = R.make_grid((60, 7, 5), dtype=R.F64, layout=R.AOSOA, aosoa_w=64)
-    assert g.pitch[0] == 64
+    assert g.pitch[0] == 64 and g.x_origin == 64
+
+
+def test_grid_rows_do_not_overlap():
+    """Every cell of [-2, n+2)^3 has its own slot inside the buffer."""
+    import numpy as np
+    for layout, w in ((R.AOS, 0), (R.SOA, 0), (R.AOSOA, 16), (R.AOSOA, 64)):
+        for dt in (R.F32, R.F64):
+            g = R.make_grid((13, 5, 4), dtype=dt, layout=layout, aosoa_w=w)
+            px, py = g.pitch[0], g.pitch[1]
+            i = np.arange(-2, 15)[None, None, :]
+            j = np.arange(-2, 7)[None, :, None]
+            k = np.arange(-2, 6)[:, None, None]
+            q = ((k + 2) * py + (j + 2)) * px + i + g.x_origin
+            assert len(np.unique(q)) == q.size
+            assert q.min() >= 0 and q.max() < g.bytes // (5 * (4 if dt == R.F32 else 8))
 
 
 @pytest.mark.parametrize("bad", [
@@ -52,6 +80,7 @@ def test_grid_init_pitches():
     dict(dtype=2), dict(layout=3), dict(layout=R.AOSOA, aosoa_w=8), dict(layout=R.SOA, aosoa_w=16),
     dict(bc=(0, 2, 0)), dict(tiling=(64, 0, 0, 0)), dict(tiling=(0, 512, 0, 0)),
     dict(tiling=(0, 0, 2, 0)), dict(tiling=(0, 0, 0, -1)), dict(tiling=(0, 0, 0, 0, 3)),
+    dict(tiling=(0, 0, 0, 0, 0, 2)), dict(tiling=(0, 0, 0, 0, 0, -1)),
     dict(n=(2000, 2000, 2000)),
 ])
 def test_grid_init_rejects(bad):
@@ -86,7 +115,7 @@ def test_partition_links_and_extents():
         assert s.nbr[3] == 4 + a + 2 * ((b + 1) % 3)
         # z: one part, transmissive -> physical
         assert s.nbr[4] == -1 and s.nbr[5] == -1
-        assert s.bytes == s.pitch[0] * s.pitch[1] * s.pitch[2] * 5 * 4
+        assert s.bytes == slots(s.pitch[0], s.pitch[1], s.pitch[2], s.x_origin) * 5 * 4
     odd = R.ripple_fv_partition(R.make_grid((11, 4, 4)), (2, 1, 1))
     assert [o.n[0] for o in odd] == [6, 5]
 

@@ -1,0 +1,117 @@
+"""The fused x-then-y sweep gives bitwise the states of the separate x and y
+sweeps, for every layout, precision, boundary condition, cells-per-thread
+choice and row length it accepts (including odd and minimum lengths); grids
+it does not accept fall back to the separate sweeps.  Also checks the
+in-place semantics of the step entry points on both paths."""
+import numpy as np
+import pytest
+import torch
+
+import gpu_util as G
+from paper_2104_08571_amd import initial_states as ist
+from paper_2104_08571_amd import ripple_fv as R
+
+pytestmark = pytest.mark.gpu
+
+
+def run_pair(shape, dtype, layout, aosoa_w, bc, nsteps, cols=0, seed=31, state=None):
+    W = state if state is not None else ist.smooth_periodic(shape, seed=seed)
+    out = []
+    for split in (0, 1):
+        g = R.make_grid(shape, dtype=dtype, layout=layout, aosoa_w=aosoa_w, bc=bc,
+                        tiling=(0, 0, 0, 0, cols, split))
+        (U,), (t,) = G.run(g, W, nsteps)
+        out.append((U, t))
+    return out
+
+
+@pytest.mark.parametrize("dtype", [R.F32, R.F64], ids=["f32", "f64"])
+@pytest.mark.parametrize("layout,w", [(R.SOA, 0), (R.AOS, 0), (R.AOSOA, 16), (R.AOSOA, 64)],
+                         ids=["soa", "aos", "aosoa16", "aosoa64"])
+@pytest.mark.parametrize("cols", [1, 2])
+def test_fused_equals_split(dtype, layout, w, cols):
+    for shape, bc in (((37, 29, 11), (1, 1, 1)), ((16, 24, 9), (0, 0, 1)), ((33, 20, 7), (0, 1, 0))):
+        (Uf, tf), (Us, ts) = run_pair(shape, dtype, layout, w, bc, 3, cols)
+        assert tf == ts, shape
+        assert np.array_equal(Uf, Us), (shape, bc)
+
+
+@pytest.mark.parametrize("nx", [16, 17, 255, 256, 257, 511, 512])
+def test_fused_row_lengths(nx):
+    """Row lengths at the ends of what one workgroup holds (1 and 2 cells per
+    thread), odd lengths, and blast (transmissive) vs periodic faces."""
+    shape = (nx, 12, 5)
+    for cols in (1, 2):
+        for bc in ((1, 1, 1), (0, 0, 0)):
+            state = ist.blast(shape) if bc[0] == 0 else None
+            (Uf, tf), (Us, ts) = run_pair(shape, R.F32, R.SOA, 0, bc, 2, cols, state=state)
+            assert tf == ts and np.array_equal(Uf, Us), (nx, cols, bc)
+
+
+@pytest.mark.parametrize("nx", [8, 15, 520])
+def test_ineligible_rows_fall_back(nx):
+    """Rows shorter than 16 or longer than a workgroup holds run the separate
+    sweeps; the fused sweep entry point reports them unsupported."""
+    shape = (nx, 10, 6)
+    (Uf, tf), (Us, ts) = run_pair(shape, R.F32, R.SOA, 0, (1, 0, 1), 3)
+    assert tf == ts and np.array_equal(Uf, Us)
+    g = R.make_grid(shape, dtype=R.F32, layout=R.SOA)
+    a, b = G.load(g, ist.smooth_periodic(shape, seed=3)), G.buffer(g)
+    with pytest.raises(R.RippleFVError) as e:
+        R.ripple_fv_sweep(G.ctx(), g, R.AXIS_XY, a.data_ptr(), b.data_ptr(), 1e-3, G.stream())
+    assert e.value.status == R.E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("dtype", [R.F32, R.F64], ids=["f32", "f64"])
+def test_sweep_axis_xy_equals_x_then_y(dtype):
+    shape = (48, 40, 13)
+    W = ist.smooth_periodic(shape, seed=41)
+    g = R.make_grid(shape, dtype=dtype, layout=R.SOA, bc=(1, 0, 1))
+    dt = 2e-3
+    a, b = G.load(g, W), G.buffer(g)
+    R.ripple_fv_sweep(G.ctx(), g, R.AXIS_XY, a.data_ptr(), b.data_ptr(), dt, G.stream())
+    fused = G.export(g, b)
+    x, y, z = G.load(g, W), G.buffer(g), G.buffer(g)
+    R.ripple_fv_sweep(G.ctx(), g, 0, x.data_ptr(), y.data_ptr(), dt, G.stream())
+    R.ripple_fv_sweep(G.ctx(), g, 1, y.data_ptr(), z.data_ptr(), dt, G.stream())
+    assert np.array_equal(fused, G.export(g, z))
+    # the input is not modified
+    assert np.array_equal(G.export(g, a), G.export(g, G.load(g, W)))
+
+
+@pytest.mark.parametrize("split", [0, 1])
+def test_step_is_in_place(split):
+    """After 1, 2 and 3 steps the state is in the first buffer on both paths."""
+    shape = (30, 26, 14)
+    W = ist.smooth_periodic(shape, seed=51)
+    g = R.make_grid(shape, dtype=R.F64, layout=R.SOA, bc=(1, 1, 1),
+                    tiling=(0, 0, 0, 0, 0, split))
+    ref = R.make_grid(shape, dtype=R.F64, layout=R.SOA, bc=(1, 1, 1),
+                      tiling=(0, 0, 0, 0, 0, 1 - split))
+    for n in (1, 2, 3):
+        (U,), _ = G.run(g, W, n)
+        (V,), _ = G.run(ref, W, n)
+        assert np.array_equal(U, V), n
+    a, b = G.load(g, W), G.buffer(g)
+    R.ripple_fv_step(G.ctx(), g, a.data_ptr(), b.data_ptr(), 0.9, 0.0, None, G.stream())
+    torch.cuda.synchronize()
+    (U1,), _ = G.run(g, W, 1)
+    assert np.array_equal(G.export(g, a), U1)
+
+
+def test_fused_batch_graph_replays():
+    """Uneven batch through the fused path: graph replays == eager == per grid."""
+    ext = [(48, 32, 16), (160, 16, 32), (96, 80, 48), (17, 33, 9)]
+    grids = [R.make_grid(e, dtype=R.F32, layout=R.SOA, bc=(1, 1, 1)) for e in ext]
+    states = [ist.smooth_periodic(e, seed=60 + i) for i, e in enumerate(ext)]
+    eager, te = G.run(grids, states, 4)
+    for flags in (R.RUN_GRAPH, R.RUN_PER_GRID, R.RUN_GRAPH | R.RUN_PER_GRID, R.RUN_GRAPH):
+        outs, ts = G.run(grids, states, 4, flags=flags)
+        assert ts == te
+        for x, y in zip(outs, eager):
+            assert np.array_equal(x, y), flags
+    split = [R.copy_grid(g, split_xy=1) for g in grids]
+    outs, ts = G.run(split, states, 4)
+    assert ts == te
+    for x, y in zip(outs, eager):
+        assert np.array_equal(x, y)

@@ -144,11 +144,7 @@ def test_halo_exchange_fills_padding():
     R.ripple_fv_halo_exchange(G.ctx(), subs, [b.data_ptr() for b in bufs], 0, G.stream())
     torch.cuda.synchronize()
 
-    def padded(s, b):
-        px, py, pz = s.pitch
-        return b.view(torch.float64).reshape(5, pz, py, px).cpu().numpy()
-
-    left, right = padded(subs[0], bufs[0]), padded(subs[1], bufs[1])
+    left, right = G.padded_cells(subs[0], bufs[0]), G.padded_cells(subs[1], bufs[1])
     nl = subs[0].n[0]
     # left block's +x padding (padded x = nl+2, nl+3) == right block's interior x = 0, 1
     assert np.array_equal(left[:, 2:-2, 2:-2, nl + 2:nl + 4], right[:, 2:-2, 2:-2, 2:4])
@@ -165,7 +161,7 @@ def test_step_api(oracle):
     a, b = G.load(g, W), G.buffer(g)
     dt = torch.zeros(1, dtype=torch.float64, device="cuda")
     R.ripple_fv_step(G.ctx(), g, a.data_ptr(), b.data_ptr(), 0.9, 0.0, dt.data_ptr(), G.stream())
-    got = G.export(g, b)
+    got = G.export(g, a)  # in place
     (ref,), _ = G.run(g, W, 1)
     assert np.array_equal(got, ref)
     U0 = oracle.prim_to_cons(W.numpy())
@@ -174,7 +170,7 @@ def test_step_api(oracle):
     # fixed dt: equals three sweeps with that dt
     a2 = G.load(g, W)
     R.ripple_fv_step(G.ctx(), g, a2.data_ptr(), b.data_ptr(), 0.9, 0.5 * dt_ref, None, G.stream())
-    got2 = G.export(g, b)
+    got2 = G.export(g, a2)
     x, y = G.load(g, W), G.buffer(g)
     R.ripple_fv_sweep(G.ctx(), g, 0, x.data_ptr(), y.data_ptr(), 0.5 * dt_ref, G.stream())
     R.ripple_fv_sweep(G.ctx(), g, 1, y.data_ptr(), x.data_ptr(), 0.5 * dt_ref, G.stream())
@@ -202,7 +198,8 @@ def test_error_paths():
     for cfl in (0.0, -0.5, 1.5, float("nan")):
         assert status("ripple_fv_step", ctx, gp, a.data_ptr(), b.data_ptr(), cfl, 0.0, None, s) == R.E_INVALID
     assert status("ripple_fv_step", ctx, gp, a.data_ptr(), b.data_ptr(), 0.9, float("inf"), None, s) == R.E_INVALID
-    assert status("ripple_fv_sweep", ctx, gp, 3, a.data_ptr(), b.data_ptr(), 0.1, s) == R.E_INVALID
+    assert status("ripple_fv_sweep", ctx, gp, 4, a.data_ptr(), b.data_ptr(), 0.1, s) == R.E_INVALID
+    assert status("ripple_fv_sweep", ctx, gp, -1, a.data_ptr(), b.data_ptr(), 0.1, s) == R.E_INVALID
     assert status("ripple_fv_sweep", ctx, gp, 0, a.data_ptr(), b.data_ptr(), -0.1, s) == R.E_INVALID
     # uninitialised descriptor (bytes not filled)
     raw = R.Grid()

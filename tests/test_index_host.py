@@ -1,0 +1,20 @@
+"""The sweeps' index arithmetic (csrc/fv_index.hpp), compiled for the host
+with g++ and checked against its plain definition over many grid shapes,
+chunk sizes and boundary modes.  No GPU needed."""
+import os
+import shutil
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_2104_08571_amd", "csrc")
+
+
+@pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
+def test_index_arithmetic(tmp_path):
+    exe = str(tmp_path / "index_check")
+    subprocess.run(["g++", "-O1", "-std=c++17", "-Wall", "-I", CSRC,
+                    os.path.join(ROOT, "tests", "index_check.cpp"), "-o", exe], check=True)
+    res = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    assert res.returncode == 0 and res.stdout.strip() == "ok", res.stdout + res.stderr
