@@ -173,11 +173,15 @@ Tiling tiling_of(const ripple_fv_grid& g) {
   t.yz_segment = g.yz_segment ? g.yz_segment : 64;
   t.persist = g.persist;
   // two x cells per y/z thread pays off where it widens the accesses (FP32
-  // SoA/AoSoA); FP64 already moves 8 bytes per lane and would lose occupancy
-  t.yz_cols = g.yz_cols ? g.yz_cols
-                        : ((g.layout != RIPPLE_FV_AOS && g.dtype == RIPPLE_FV_F32) ? 2 : 1);
+  // SoA/AoSoA); FP64 always runs one (two FP64 cells per thread do not fit
+  // the register file without spilling)
+  if (g.dtype == RIPPLE_FV_F64) {
+    t.yz_cols = t.xy_cols = 1;
+  } else {
+    t.yz_cols = g.yz_cols ? g.yz_cols : (g.layout != RIPPLE_FV_AOS ? 2 : 1);
+    t.xy_cols = g.yz_cols ? g.yz_cols : 1;
+  }
   t.split_xy = g.split_xy;
-  t.xy_cols = g.yz_cols ? g.yz_cols : 1;
   return t;
 }
 
@@ -1134,7 +1138,7 @@ extern "C" ripple_fv_status ripple_fv_batch_tune(ripple_fv_ctx* ctx, int32_t n,
     }
   // 4. x cells per y/z thread, fused or separate x and y sweeps
   for (int cols : {1, 2}) {
-    if (st) break;
+    if (st || base[0].dtype == RIPPLE_FV_F64) break;  // FP64 runs one cell per thread
     st = consider(with([&](ripple_fv_grid& g) { g.yz_cols = cols; }));
   }
   for (int split : {0, 1}) {

@@ -952,9 +952,11 @@ static hipError_t sweep_typed(int axis, const Tiling& tl, const SweepParams& p, 
       hipLaunchKernelGGL((k_sweep_x<T, LAY, 128>), dim3(blocks), dim3(128), 0, s, p, G, TS, L);
     else
       hipLaunchKernelGGL((k_sweep_x<T, LAY, 256>), dim3(blocks), dim3(256), 0, s, p, G, TS, L);
-  } else if (tl.yz_cols == 2) {
-    return sweep_yz_cols<T, LAY, 2>(axis, tl, p, blocks, s);
   } else {
+    // FP64 runs one cell per thread only (see sweep_xy_typed)
+    if constexpr (sizeof(T) == 4) {
+      if (tl.yz_cols == 2) return sweep_yz_cols<T, LAY, 2>(axis, tl, p, blocks, s);
+    }
     return sweep_yz_cols<T, LAY, 1>(axis, tl, p, blocks, s);
   }
   return hipGetLastError();
@@ -984,10 +986,15 @@ static hipError_t sweep_xy_typed(const Tiling& tl, const SweepParams& p, int blo
   const DevGrid* G = p.w.grids;
   const int64_t* TS = p.tiles.tile_start;
   const double* L = p.w.lam;
-  if (tl.yz_cols == 2)
-    hipLaunchKernelGGL((k_sweep_xy<T, LAY, 2, xy_threads(2)>), dim3(blocks), dim3(xy_threads(2)), 0, s, p, G, TS, L);
-  else
-    hipLaunchKernelGGL((k_sweep_xy<T, LAY, 1, xy_threads(1)>), dim3(blocks), dim3(xy_threads(1)), 0, s, p, G, TS, L);
+  // FP64 runs one cell per thread only (tiling_of resolves it so): two FP64
+  // cells per thread exceed the register file and are not instantiated.
+  if constexpr (sizeof(T) == 4) {
+    if (tl.xy_cols == 2) {
+      hipLaunchKernelGGL((k_sweep_xy<T, LAY, 2, xy_threads(2)>), dim3(blocks), dim3(xy_threads(2)), 0, s, p, G, TS, L);
+      return hipGetLastError();
+    }
+  }
+  hipLaunchKernelGGL((k_sweep_xy<T, LAY, 1, xy_threads(1)>), dim3(blocks), dim3(xy_threads(1)), 0, s, p, G, TS, L);
   return hipGetLastError();
 }
 

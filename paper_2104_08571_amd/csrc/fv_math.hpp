@@ -17,9 +17,10 @@
 // velocities and kinetic energy are formed by multiplication.  The build
 // disables implicit contraction; fused multiply-adds appear only where written
 // (fma_ below), so every inlined copy of these functions -- in every layout,
-// tiling, batched or partitioned variant, prologue or loop body -- performs
-// the same operations on a cell and produces the same bits.  Expression order
-// otherwise follows the textbook formulas.
+// tiling, batched, fused or partitioned variant, prologue or loop body --
+// performs the same operations on a cell and produces the same bits.
+// Expressions follow the textbook formulas except where a rearrangement saves
+// ALU work; each such place says so.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -34,6 +35,8 @@ template <> struct Arith<float> {
     return a * __builtin_amdgcn_rcpf(b);
   }
   static __device__ __forceinline__ float root(float x) { return __builtin_amdgcn_sqrtf(x); }
+  static __device__ __forceinline__ float min(float a, float b) { return __builtin_fminf(a, b); }
+  static __device__ __forceinline__ float max(float a, float b) { return __builtin_fmaxf(a, b); }
   // minmod(a, b) is the median of (a, b, 0).
   static __device__ __forceinline__ float minmod(float a, float b) {
     return __builtin_amdgcn_fmed3f(a, b, 0.0f);
@@ -44,6 +47,8 @@ template <> struct Arith<double> {
   static __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
   static __device__ __forceinline__ double quot(double a, double b) { return a / b; }
   static __device__ __forceinline__ double root(double x) { return __builtin_sqrt(x); }
+  static __device__ __forceinline__ double min(double a, double b) { return __builtin_fmin(a, b); }
+  static __device__ __forceinline__ double max(double a, double b) { return __builtin_fmax(a, b); }
   static __device__ __forceinline__ double minmod(double a, double b) {
     return __builtin_fmax(__builtin_fmin(a, b), __builtin_fmin(__builtin_fmax(a, b), 0.0));
   }
@@ -55,12 +60,12 @@ __device__ __forceinline__ double fma_(double a, double b, double c) { return __
 template <typename T> __device__ __forceinline__ T gamma_() { return T(1.4); }
 template <typename T> __device__ __forceinline__ T gamma_m1() { return T(1.4) - T(1); }
 
-// p = (gamma - 1) (E - |m|^2 / (2 rho)), given rinv = 1 / rho.
+// p = (gamma - 1) (E - |m|^2 / (2 rho)), given rinv = 1 / rho, evaluated as
+// (gamma - 1) E - ((gamma - 1) / 2) |m|^2 rinv.
 template <typename T>
 __device__ __forceinline__ T pressure(const T u[5], T rinv) {
   const T m2 = fma_(u[3], u[3], fma_(u[2], u[2], u[1] * u[1]));
-  const T kinetic = T(0.5) * m2 * rinv;
-  return gamma_m1<T>() * (u[4] - kinetic);
+  return fma_(T(-0.5) * gamma_m1<T>() * m2, rinv, gamma_m1<T>() * u[4]);
 }
 
 // Physical flux along D given the normal velocity un and pressure p.
@@ -104,48 +109,55 @@ __device__ __forceinline__ void hancock(const T u0[5], const T dm[5], const T dp
 // HLLC flux along D between left state ul and right state ur.  Davis wave
 // speeds; contact speed S* (Toro eq. 10.37); star state (eq. 10.39); flux
 // selection (eq. 10.26) with ties resolved as 0 <= S_L, 0 <= S*, 0 < S_R.
-// Only the side the contact speed selects is evaluated.
+// Only the side the contact speed selects is evaluated.  Rearranged for the
+// ALU, with the same value up to rounding:
+//   rho u = m (the normal momentum) in S*'s numerator;
+//   with q = 1 / (S_k - S*): star state = (rho_k, m_k, E_k) * g + extra terms,
+//   g = (S_k - u_k) q, and p_k / (rho_k (S_k - u_k)) * factor = p_k q;
+//   the supersonic cases use F_k + min(S_L, 0) (U*_L - U_L) (left) or
+//   F_k + max(S_R, 0) (U*_R - U_R) (right), whose correction vanishes
+//   exactly when the flux is F_L or F_R.
 template <typename T, int D>
 __device__ __forceinline__ void hllc(const T ul[5], const T ur[5], T f[5]) {
   using A = Arith<T>;
   const T rl = A::recip(ul[0]);
   const T rr = A::recip(ur[0]);
-  const T uL = ul[1 + D] * rl;
-  const T uR = ur[1 + D] * rr;
+  const T mL = ul[1 + D], mR = ur[1 + D];
+  const T uL = mL * rl;
+  const T uR = mR * rr;
   const T pL = pressure(ul, rl);
   const T pR = pressure(ur, rr);
   const T cL = A::root(gamma_<T>() * pL * rl);
   const T cR = A::root(gamma_<T>() * pR * rr);
-  const T SL = __builtin_fmin(uL - cL, uR - cR);
-  const T SR = __builtin_fmax(uL + cL, uR + cR);
+  const T SL = A::min(uL - cL, uR - cR);
+  const T SR = A::max(uL + cL, uR + cR);
   const T aL = SL - uL, aR = SR - uR;
-  const T num = fma_(-(ur[0] * uR), aR, fma_(ul[0] * uL, aL, pR - pL));
+  const T num = fma_(-mR, aR, fma_(mL, aL, pR - pL));
   const T den = fma_(ul[0], aL, -(ur[0] * aR));
   const T Ss = A::quot(num, den);
 
   const bool left = (T(0) <= SL) || (T(0) <= Ss);
-  const bool supersonic = (T(0) <= SL) || (!left && !(T(0) < SR));
   T uk[5];
 #pragma unroll
   for (int c = 0; c < 5; ++c) uk[c] = left ? ul[c] : ur[c];
-  const T rk = left ? rl : rr;
   const T unk = left ? uL : uR;
   const T pk = left ? pL : pR;
   const T Sk = left ? SL : SR;
+  const T Sc = left ? A::min(SL, T(0)) : A::max(SR, T(0));
 
   T fk[5];
   flux<T, D>(uk, unk, pk, fk);
-  const T Ak = uk[0] * (Sk - unk);
-  const T factor = A::quot(Ak, Sk - Ss);
+  const T q = A::recip(Sk - Ss);
+  const T g = (Sk - unk) * q;                // factor / rho_k
   T us[5];
-  us[0] = factor;
-  us[1] = factor * (uk[1] * rk);
-  us[2] = factor * (uk[2] * rk);
-  us[3] = factor * (uk[3] * rk);
-  us[1 + D] = factor * Ss;
-  us[4] = factor * fma_(Ss - unk, Ss + A::quot(pk, Ak), uk[4] * rk);
+  us[0] = uk[0] * g;
+  us[1] = uk[1] * g;
+  us[2] = uk[2] * g;
+  us[3] = uk[3] * g;
+  us[1 + D] = us[0] * Ss;
+  us[4] = fma_(Ss - unk, fma_(us[0], Ss, pk * q), uk[4] * g);
 #pragma unroll
-  for (int c = 0; c < 5; ++c) f[c] = supersonic ? fk[c] : fma_(Sk, us[c] - uk[c], fk[c]);
+  for (int c = 0; c < 5; ++c) f[c] = fma_(Sc, us[c] - uk[c], fk[c]);
 }
 
 // Conservative update U' = U - lam (F_{i+1/2} - F_{i-1/2}).

@@ -38,10 +38,11 @@ def test_fused_equals_split(dtype, layout, w, cols):
 
 @pytest.mark.parametrize("nx", [16, 17, 255, 256, 257, 511, 512])
 def test_fused_row_lengths(nx):
-    """Row lengths at the ends of what one workgroup holds (1 and 2 cells per
-    thread), odd lengths, and blast (transmissive) vs periodic faces."""
-    shape = (nx, 12, 5)
-    for cols in (1, 2):
+    """Row lengths at the ends of what one workgroup holds (default, 1 and 2
+    cells per thread), odd lengths, and blast (transmissive) vs periodic
+    faces; enough z planes that tiles hold several rows."""
+    shape = (nx, 12, 37)
+    for cols in (0, 1, 2):
         for bc in ((1, 1, 1), (0, 0, 0)):
             state = ist.blast(shape) if bc[0] == 0 else None
             (Uf, tf), (Us, ts) = run_pair(shape, R.F32, R.SOA, 0, bc, 2, cols, state=state)
