@@ -110,7 +110,7 @@ enum ripple_fv_kernel_kind {
  *           change results.
  *           x_block: threads per workgroup of the x sweep (128, 256);
  *           yz_block: threads per workgroup of the y/z sweeps (64, 128, 256);
- *           yz_segment: cells each y/z thread advances (>= 4);
+ *           yz_segment: cells each y/z thread advances (>= 4; 0 = 128);
  *           persist: workgroups per CU of persistent launches (0 = one per tile);
  *           yz_cols: adjacent x cells per y/z thread (1, 2; 0 = 2 for FP32
  *           SoA/AoSoA, else 1); in the fused x-y sweep, cells per thread of

@@ -170,7 +170,7 @@ Tiling tiling_of(const ripple_fv_grid& g) {
   Tiling t;
   t.x_block = g.x_block ? g.x_block : 256;
   t.yz_block = g.yz_block ? g.yz_block : 256;
-  t.yz_segment = g.yz_segment ? g.yz_segment : 64;
+  t.yz_segment = g.yz_segment ? g.yz_segment : 128;
   t.persist = g.persist;
   // two x cells per y/z thread pays off where it widens the accesses (FP32
   // SoA/AoSoA); FP64 always runs one (two FP64 cells per thread do not fit
