@@ -112,10 +112,10 @@ enum ripple_fv_kernel_kind {
  *           yz_block: threads per workgroup of the y/z sweeps (64, 128, 256);
  *           yz_segment: cells each y/z thread advances (>= 4; 0 = 128);
  *           persist: workgroups per CU of persistent launches (0 = one per tile);
- *           yz_cols: adjacent x cells per y/z thread (1, 2; 0 = 2 for FP32
- *           SoA/AoSoA, else 1); in the fused x-y sweep, cells per thread of
- *           workgroups of 512 / yz_cols threads (0 = 1 there); FP64 always
- *           runs 1 (2 is accepted and means 1);
+ *           yz_cols: adjacent x cells per thread of the separate y and z
+ *           sweeps (1, 2; 0 = 2 for FP32 SoA/AoSoA, else 1); FP64 always
+ *           runs 1 (2 is accepted and means 1); the fused x-y sweep always
+ *           runs one cell per thread in workgroups of 512;
  *           split_xy: 0 = run the x and y sweeps as one fused pass wherever
  *           a grid allows it (x and y faces not linked to sub-blocks, and
  *           16 <= n[0] <= 512), 1 = always as two separate sweeps

@@ -175,12 +175,11 @@ Tiling tiling_of(const ripple_fv_grid& g) {
   // two x cells per y/z thread pays off where it widens the accesses (FP32
   // SoA/AoSoA); FP64 always runs one (two FP64 cells per thread do not fit
   // the register file without spilling)
-  if (g.dtype == RIPPLE_FV_F64) {
-    t.yz_cols = t.xy_cols = 1;
-  } else {
+  if (g.dtype == RIPPLE_FV_F64)
+    t.yz_cols = 1;
+  else
     t.yz_cols = g.yz_cols ? g.yz_cols : (g.layout != RIPPLE_FV_AOS ? 2 : 1);
-    t.xy_cols = g.yz_cols ? g.yz_cols : 1;
-  }
+  t.xy_cols = 1;  // the fused x-y sweep runs one cell per thread
   t.split_xy = g.split_xy;
   return t;
 }

@@ -71,7 +71,7 @@ struct Tiling {
   int persist;     // workgroups per CU for persistent launches, 0 = one per tile
   int yz_cols;     // adjacent x cells per thread in the y/z sweeps (1 or 2)
   int split_xy;    // 1: separate x and y sweeps even where they could be fused
-  int xy_cols;     // adjacent x cells per thread in the fused x-y sweep (1 or 2)
+  int xy_cols;     // x cells per thread in the fused x-y sweep (always 1)
 };
 
 int lay_of(const ripple_fv_grid& g);

@@ -357,6 +357,22 @@ __global__ void __launch_bounds__(256) k_sweep_yz(SweepParams p, const DevGrid* 
 //
 // Rings (period 3): raw rows are loaded three iterations before they are
 // x-swept; x-swept rows j, j+1, j+2 are held while cell j is updated.
+// Iterations per trip of the marching loop, a multiple of the ring period 3.
+// Loads issued in an earlier trip are waited for at a trip's first use (the
+// wait counter is merged conservatively at the loop head), so longer trips
+// keep a little more in flight.  Measured at 512^3, FP32: 3 -> 1.444 ms,
+// 6 -> 1.394, 9 -> 1.387, 12 -> 1.397; FP64: 3.874 / 3.852 / 3.888 / 3.902,
+// and at 15 the FP64 loop outgrows the instruction cache (5.27 ms).
+#ifndef RFV_XY_UNROLL_F32
+#define RFV_XY_UNROLL_F32 9
+#endif
+#ifndef RFV_XY_UNROLL_F64
+#define RFV_XY_UNROLL_F64 6
+#endif
+template <typename T> constexpr int xy_unroll() {
+  return sizeof(T) == 4 ? RFV_XY_UNROLL_F32 : RFV_XY_UNROLL_F64;
+}
+
 template <typename T, int LAY, int CX, int NT>
 __global__ void __launch_bounds__(NT) k_sweep_xy(SweepParams p, const DevGrid* __restrict__ grids,
                                                  const int64_t* __restrict__ tile_start,
@@ -570,13 +586,15 @@ __global__ void __launch_bounds__(NT) k_sweep_xy(SweepParams p, const DevGrid* _
       }
     }
 
-    // Iteration o (cell j = j0 + o), k = o mod 3: xs[(k+2)%3] = U_j,
-    // xs[k] = U_{j+1}; row j+2 is x-swept from raw[(k+1)%3] into
+    // Iteration o (cell j = j0 + o), k = o mod U: xs[(k+2)%3] = U_j,
+    // xs[k%3] = U_{j+1}; row j+2 is x-swept from raw[(k+1)%3] into
     // xs[(k+1)%3] (the slot of U_{j-1}), and row j+5 is loaded into the raw
     // slot just consumed.  dprev = U_{j+1} - U_j, brp = Ub^R_j, fprev = F_{j-1/2}.
-    for (int o0 = 0; o0 < len; o0 += 3) {
+    constexpr int U = xy_unroll<T>();
+    static_assert(U % 3 == 0, "the loop must advance the rings by whole periods");
+    for (int o0 = 0; o0 < len; o0 += U) {
 #pragma unroll
-      for (int k = 0; k < 3; ++k) {
+      for (int k = 0; k < U; ++k) {
         const int o = o0 + k;
         if (o >= len) break;
         const int j = j0 + o;
@@ -586,7 +604,7 @@ __global__ void __launch_bounds__(NT) k_sweep_xy(SweepParams p, const DevGrid* _
 #pragma unroll
         for (int m = 0; m < CX; ++m) {
           const T* uj = xs[(k + 2) % 3][m];
-          const T* uj1 = xs[k][m];
+          const T* uj1 = xs[k % 3][m];
           const T* uj2 = xs[(k + 1) % 3][m];
 #pragma unroll
           for (int c = 0; c < 5; ++c) dnext[c] = uj2[c] - uj1[c];
@@ -982,19 +1000,11 @@ hipError_t launch_sweep(int dtype, int lay, int axis, const Tiling& tl, const Sw
 }
 
 template <typename T, int LAY>
-static hipError_t sweep_xy_typed(const Tiling& tl, const SweepParams& p, int blocks, hipStream_t s) {
-  const DevGrid* G = p.w.grids;
-  const int64_t* TS = p.tiles.tile_start;
-  const double* L = p.w.lam;
-  // FP64 runs one cell per thread only (tiling_of resolves it so): two FP64
-  // cells per thread exceed the register file and are not instantiated.
-  if constexpr (sizeof(T) == 4) {
-    if (tl.xy_cols == 2) {
-      hipLaunchKernelGGL((k_sweep_xy<T, LAY, 2, xy_threads(2)>), dim3(blocks), dim3(xy_threads(2)), 0, s, p, G, TS, L);
-      return hipGetLastError();
-    }
-  }
-  hipLaunchKernelGGL((k_sweep_xy<T, LAY, 1, xy_threads(1)>), dim3(blocks), dim3(xy_threads(1)), 0, s, p, G, TS, L);
+static hipError_t sweep_xy_typed(const Tiling&, const SweepParams& p, int blocks, hipStream_t s) {
+  // one cell per thread: with two, the deep unroll that hides the memory
+  // latency no longer fits the register file (and was slower when it did)
+  hipLaunchKernelGGL((k_sweep_xy<T, LAY, 1, xy_threads(1)>), dim3(blocks), dim3(xy_threads(1)), 0, s,
+                     p, p.w.grids, p.tiles.tile_start, p.w.lam);
   return hipGetLastError();
 }
 

@@ -1,8 +1,8 @@
 """The fused x-then-y sweep gives bitwise the states of the separate x and y
-sweeps, for every layout, precision, boundary condition, cells-per-thread
-choice and row length it accepts (including odd and minimum lengths); grids
-it does not accept fall back to the separate sweeps.  Also checks the
-in-place semantics of the step entry points on both paths."""
+sweeps, for every layout, precision, boundary condition and row length;
+grids it does not accept (rows outside 16..512 cells, x or y faces linked to
+sub-blocks) fall back to the separate sweeps with the same results.  Also
+checks the in-place semantics of the step entry points on both paths."""
 import numpy as np
 import pytest
 import torch
@@ -36,30 +36,45 @@ def test_fused_equals_split(dtype, layout, w, cols):
         assert np.array_equal(Uf, Us), (shape, bc)
 
 
-@pytest.mark.parametrize("nx", [16, 17, 255, 256, 257, 511, 512])
+@pytest.mark.parametrize("nx", [2, 3, 16, 17, 56, 57, 58, 59, 60, 61, 62, 255, 512, 520, 1000])
 def test_fused_row_lengths(nx):
-    """Row lengths at the ends of what one workgroup holds (default, 1 and 2
-    cells per thread), odd lengths, and blast (transmissive) vs periodic
-    faces; enough z planes that tiles hold several rows."""
-    shape = (nx, 12, 37)
-    for cols in (0, 1, 2):
-        for bc in ((1, 1, 1), (0, 0, 0)):
-            state = ist.blast(shape) if bc[0] == 0 else None
-            (Uf, tf), (Us, ts) = run_pair(shape, R.F32, R.SOA, 0, bc, 2, cols, state=state)
-            assert tf == ts and np.array_equal(Uf, Us), (nx, cols, bc)
+    """Row lengths from 2 to 1000 cells: below, inside and above what one
+    workgroup holds (fused where 16 <= n0 <= 512, separate sweeps
+    otherwise), odd lengths; blast (transmissive) vs periodic faces; several
+    z planes per tile."""
+    shape = (nx, 9, 7)
+    for bc in ((1, 1, 1), (0, 0, 0)):
+        # the blast needs a few cells across it to stay physical
+        state = ist.blast(shape) if bc[0] == 0 and nx >= 16 else None
+        (Uf, tf), (Us, ts) = run_pair(shape, R.F32, R.SOA, 0, bc, 2, 0, state=state)
+        assert tf == ts and np.array_equal(Uf, Us), (nx, bc)
 
 
-@pytest.mark.parametrize("nx", [8, 15, 520])
-def test_ineligible_rows_fall_back(nx):
-    """Rows shorter than 16 or longer than a workgroup holds run the separate
-    sweeps; the fused sweep entry point reports them unsupported."""
-    shape = (nx, 10, 6)
-    (Uf, tf), (Us, ts) = run_pair(shape, R.F32, R.SOA, 0, (1, 0, 1), 3)
-    assert tf == ts and np.array_equal(Uf, Us)
-    g = R.make_grid(shape, dtype=R.F32, layout=R.SOA)
-    a, b = G.load(g, ist.smooth_periodic(shape, seed=3)), G.buffer(g)
+def test_linked_sub_blocks_fall_back():
+    """Sub-blocks linked to neighbours run the separate sweeps with halo
+    copies and match the whole grid (which runs fused); the fused sweep entry
+    point reports a linked grid unsupported."""
+    shape = (30, 24, 10)
+    whole = R.make_grid(shape, dtype=R.F64, layout=R.SOA, bc=(1, 0, 1))
+    W = ist.smooth_periodic(shape, seed=77)
+    (ref,), (t_ref,) = G.run(whole, W, 3)
+    for parts in ((1, 2, 1), (2, 1, 1), (3, 1, 2)):
+        subs = R.ripple_fv_partition(whole, parts)
+        states, origins = [], []
+        for idx, sb in enumerate(subs):
+            a, b, c = idx % parts[0], (idx // parts[0]) % parts[1], idx // (parts[0] * parts[1])
+            o = [k * (n // m) + min(k, n % m) for k, n, m in zip((a, b, c), shape, parts)]
+            origins.append(o)
+            states.append(ist.smooth_periodic(list(sb.n), 77, origin=o, n_global=shape))
+        outs, ts = G.run(subs, states, 3)
+        for sb, U, o, t in zip(subs, outs, origins, ts):
+            assert t == t_ref
+            part = ref[:, o[2]:o[2] + sb.n[2], o[1]:o[1] + sb.n[1], o[0]:o[0] + sb.n[0]]
+            assert np.array_equal(U, part), (parts, o)
+    sub = R.ripple_fv_partition(whole, (1, 2, 1))[0]
+    a, b = G.buffer(sub), G.buffer(sub)
     with pytest.raises(R.RippleFVError) as e:
-        R.ripple_fv_sweep(G.ctx(), g, R.AXIS_XY, a.data_ptr(), b.data_ptr(), 1e-3, G.stream())
+        R.ripple_fv_sweep(G.ctx(), sub, R.AXIS_XY, a.data_ptr(), b.data_ptr(), 1e-3, G.stream())
     assert e.value.status == R.E_UNSUPPORTED
 
 
