@@ -12,8 +12,9 @@
 // Components are (rho, m_x, m_y, m_z, E); D selects the normal momentum.
 //
 // Precision notes.  FP32 uses the hardware reciprocal and square root
-// (v_rcp_f32, v_sqrt_f32, 1 ulp) and v_med3_f32 for minmod; FP64 uses IEEE
-// division and square root.  Each density is inverted once per state and
+// (v_rcp_f32, v_sqrt_f32, 1 ulp) and v_med3_f32 for minmod; FP64 uses the
+// hardware estimates refined by Newton steps (about an ulp) in the sweeps and
+// IEEE division and square root for the wave speeds.  Each density is inverted once per state and
 // velocities and kinetic energy are formed by multiplication.  The build
 // disables implicit contraction; fused multiply-adds appear only where written
 // (fma_ below), so every inlined copy of these functions -- in every layout,
@@ -43,10 +44,26 @@ template <> struct Arith<float> {
   }
 };
 
+// FP64 reciprocal and square root for the sweeps: the hardware estimates
+// (v_rcp_f64, v_rsq_f64, about 2^-24 relative error) refined by two Newton
+// steps each, which brings them to within about an ulp in 5 and 9
+// instructions, where IEEE division and square root expand to longer
+// sequences.  Positive finite arguments only (the sweeps' densities, sound
+// speeds and wave-speed differences); the time step uses IEEE operations.
 template <> struct Arith<double> {
-  static __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
-  static __device__ __forceinline__ double quot(double a, double b) { return a / b; }
-  static __device__ __forceinline__ double root(double x) { return __builtin_sqrt(x); }
+  static __device__ __forceinline__ double recip(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+    return __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+  }
+  static __device__ __forceinline__ double quot(double a, double b) { return a * recip(b); }
+  static __device__ __forceinline__ double root(double x) {
+    const double h = 0.5 * x;
+    double y = __builtin_amdgcn_rsq(x);
+    y = __builtin_fma(y, __builtin_fma(-h * y, y, 0.5), y);
+    y = __builtin_fma(y, __builtin_fma(-h * y, y, 0.5), y);
+    return x * y;
+  }
   static __device__ __forceinline__ double min(double a, double b) { return __builtin_fmin(a, b); }
   static __device__ __forceinline__ double max(double a, double b) { return __builtin_fmax(a, b); }
   static __device__ __forceinline__ double minmod(double a, double b) {
@@ -170,9 +187,12 @@ __device__ __forceinline__ void update(const T u[5], T lam, const T fp[5], const
 // |u_d| + c for d = x, y, z; `bad` when rho <= 0, p <= 0 or a value is not finite.
 template <typename T>
 __device__ __forceinline__ void wavespeeds(const T u[5], T s[3], bool& bad) {
-  const T r = Arith<T>::recip(u[0]);
+  // FP64: IEEE division and square root, so the time step matches a
+  // reference computed with them to the last bits
+  const T r = sizeof(T) == 8 ? T(1) / u[0] : Arith<T>::recip(u[0]);
   const T p = pressure(u, r);
-  const T c = Arith<T>::root(gamma_<T>() * p * r);
+  const T c = sizeof(T) == 8 ? T(__builtin_sqrt(double(gamma_<T>() * p * r)))
+                             : Arith<T>::root(gamma_<T>() * p * r);
   const T inf = T(__builtin_huge_val());
 #pragma unroll
   for (int d = 0; d < 3; ++d) s[d] = __builtin_fabs(u[1 + d] * r) + c;
