@@ -117,8 +117,9 @@ enum ripple_fv_kernel_kind {
  *           runs 1 (2 is accepted and means 1); the fused x-y sweep always
  *           runs one cell per thread in workgroups of 512;
  *           split_xy: 0 = run the x and y sweeps as one fused pass wherever
- *           a grid allows it (x and y faces not linked to sub-blocks, and
- *           16 <= n[0] <= 512), 1 = always as two separate sweeps
+ *           every grid of the batch allows it (16 <= n[0] <= 512, or <= 508
+ *           when an x face is linked to a sub-block), 1 = always as two
+ *           separate sweeps
  *  reserved must be 0
  *  x_origin OUT: padded x index of interior cell x = 0 (see below)
  *  pitch, bytes   OUT: padded extents (Px, Py, Pz) and bytes of one buffer

@@ -179,7 +179,6 @@ Tiling tiling_of(const ripple_fv_grid& g) {
     t.yz_cols = 1;
   else
     t.yz_cols = g.yz_cols ? g.yz_cols : (g.layout != RIPPLE_FV_AOS ? 2 : 1);
-  t.xy_cols = 1;  // the fused x-y sweep runs one cell per thread
   t.split_xy = g.split_xy;
   return t;
 }
@@ -301,11 +300,10 @@ ripple_fv_status build_plan(ripple_fv_ctx* ctx, int n, const ripple_fv_grid* gri
   P->tl = tiling_of(grids[0]);
   P->grids.assign(grids, grids + n);
   P->fused = !P->tl.split_xy;
-  for (int g = 0; g < n; ++g) P->fused = P->fused && xy_eligible(grids[g], P->tl.xy_cols);
+  for (int g = 0; g < n; ++g) P->fused = P->fused && xy_eligible(grids[g]);
   for (int k = 0; k < 5; ++k) P->tiles[k].assign(n + 1, 0);
   for (int g = 0; g < n; ++g) {
-    P->tiles[4][g + 1] = P->tiles[4][g] + (P->fused ? tiles_xy(grids[g], P->tl.yz_segment,
-                                                               P->tl.xy_cols) : 0);
+    P->tiles[4][g + 1] = P->tiles[4][g] + (P->fused ? tiles_xy(grids[g], P->tl.yz_segment) : 0);
     P->tiles[0][g + 1] = P->tiles[0][g] + tiles_x(grids[g], P->tl.x_block);
     P->tiles[1][g + 1] = P->tiles[1][g] + tiles_yz(grids[g], 1, P->tl.yz_block, P->tl.yz_segment,
                                                    P->tl.yz_cols);
@@ -535,13 +533,15 @@ ripple_fv_status enqueue_sweep_xy(ripple_fv_ctx* ctx, Plan* P, Launcher& L, int 
   return L.end(e1);
 }
 
-ripple_fv_status enqueue_halo(ripple_fv_ctx* ctx, Plan* P, Launcher& L, int axis, int buf) {
+ripple_fv_status enqueue_halo(ripple_fv_ctx* ctx, Plan* P, Launcher& L, int axis, int buf,
+                              int ext = 0) {
   if (P->halo[axis].empty()) return RIPPLE_FV_OK;
   hipEvent_t e1 = nullptr;
   ripple_fv_status st = L.begin(RIPPLE_FV_K_HALO, &e1);
   if (st) return st;
-  LAUNCH_OR_FAIL(ctx, launch_halo(P->dtype, P->lay, P->work(ctx->flag), buf, axis, P->d_halo[axis],
-                                  (int)P->halo[axis].size(), P->halo_area[axis], L.s));
+  LAUNCH_OR_FAIL(ctx, launch_halo(P->dtype, P->lay, P->work(ctx->flag), buf, axis, ext,
+                                  P->d_halo[axis], (int)P->halo[axis].size(),
+                                  P->halo_area[axis], L.s));
   return L.end(e1);
 }
 
@@ -587,6 +587,10 @@ ripple_fv_status enqueue_step(ripple_fv_ctx* ctx, Plan* P, Launcher& L, int cur,
   const int oth = 1 - cur;
   ripple_fv_status st = enqueue_dt(ctx, P, L, cfl, fixed_dt, 1, dt_out);
   if (P->fused) {
+    // the fused pass x-sweeps the y padding rows itself: they take the raw
+    // neighbour rows first, then the x copy covers them too (corner cells)
+    if (!st) st = enqueue_halo(ctx, P, L, 1, cur);
+    if (!st) st = enqueue_halo(ctx, P, L, 0, cur, HALO);
     if (!st) st = enqueue_sweep_xy(ctx, P, L, cur, oth, per_grid);
     if (!st) st = enqueue_halo(ctx, P, L, 2, oth);
     if (!st) st = enqueue_sweep(ctx, P, L, 2, oth, cur, 1, per_grid);
@@ -839,9 +843,11 @@ ripple_fv_status ripple_fv_sweep(ripple_fv_ctx* ctx, const ripple_fv_grid* g, in
   Launcher L{ctx, s, false, {}, 0};
   if ((st = enqueue_dt(ctx, P, L, 1.0, dt, 0, nullptr))) return st;
   if (axis == RIPPLE_FV_AXIS_XY) {
-    if (!P->fused)
+    // a linked grid would need the corner padding that run_batch fills
+    const bool linked = g->nbr[0] >= 0 || g->nbr[1] >= 0 || g->nbr[2] >= 0 || g->nbr[3] >= 0;
+    if (!P->fused || linked)
       return fail(ctx, RIPPLE_FV_E_UNSUPPORTED,
-                  "fused x-y sweep needs unlinked x and y faces, 16 <= n[0] <= 512 and split_xy = 0");
+                  "fused x-y sweep needs 16 <= n[0] <= 512, unlinked x and y faces and split_xy = 0");
     return enqueue_sweep_xy(ctx, P, L, 0, 1, false);
   }
   return enqueue_sweep(ctx, P, L, axis, 0, 1, 0, false);

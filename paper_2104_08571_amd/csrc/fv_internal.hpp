@@ -71,7 +71,6 @@ struct Tiling {
   int persist;     // workgroups per CU for persistent launches, 0 = one per tile
   int yz_cols;     // adjacent x cells per thread in the y/z sweeps (1 or 2)
   int split_xy;    // 1: separate x and y sweeps even where they could be fused
-  int xy_cols;     // x cells per thread in the fused x-y sweep (always 1)
 };
 
 int lay_of(const ripple_fv_grid& g);
@@ -80,12 +79,12 @@ int lay_of(const ripple_fv_grid& g);
 int64_t tiles_x(const ripple_fv_grid& g, int x_block);
 int64_t tiles_yz(const ripple_fv_grid& g, int axis, int yz_block, int yz_segment, int yz_cols);
 int64_t tiles_ws(const ripple_fv_grid& g);
-// Fused x-then-y sweep: workgroups of xy_threads(cols) lanes owning `cols`
-// adjacent x cells each, over whole x rows of nx >= XY_MIN_NX cells.
+// Fused x-then-y sweep: workgroups of XY_THREADS lanes owning whole x rows
+// (one lane per cell, plus four ghost lanes per row when an x face is linked).
 constexpr int XY_MIN_NX = 16;
-constexpr int xy_threads(int cols) { return 512 / cols; }
-bool xy_eligible(const ripple_fv_grid& g, int cols);
-int64_t tiles_xy(const ripple_fv_grid& g, int yz_segment, int cols);
+constexpr int XY_THREADS = 512;
+bool xy_eligible(const ripple_fv_grid& g);
+int64_t tiles_xy(const ripple_fv_grid& g, int yz_segment);
 constexpr int WS_BLOCK = 256;
 constexpr int WS_CELLS_PER_THREAD = 4;
 
@@ -98,8 +97,9 @@ hipError_t launch_wavespeed(int dtype, int lay, const Work& w, int in, TileRange
                             unsigned long long* s_out, int grid_blocks, hipStream_t s);
 hipError_t launch_dt(const Work& w, double cfl, double fixed_dt, int reset_s, double* dt_out,
                      hipStream_t s);
-hipError_t launch_halo(int dtype, int lay, const Work& w, int buf, int axis, const HaloTask* tasks,
-                       int ntasks, int64_t max_area, hipStream_t s);
+// ext: padding layers to cover on each side of the first axis across the face
+hipError_t launch_halo(int dtype, int lay, const Work& w, int buf, int axis, int ext,
+                       const HaloTask* tasks, int ntasks, int64_t max_area, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s);
 hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t s);
 

@@ -344,19 +344,26 @@ __global__ void __launch_bounds__(256) k_sweep_yz(SweepParams p, const DevGrid* 
 // of k_sweep_x followed by k_sweep_yz along y, so the result is bitwise that
 // of the two separate kernels.
 //
-// Tile = (R whole x rows at consecutive z, R = NT / groups per row) x
-// (segment of p.seg rows along y).  Lane t owns the CX cells i0 .. i0+CX-1 of
-// row slot t / groups.  Per loaded row: publish the cells (and the x ghost
-// cells the boundary condition defines) to LDS; reconstruct own cells and
-// publish the right evolved state of the last one; compute the left face flux
-// of each own cell and publish the first; update.  The x ghost reconstruction
-// and the right-most face come from the periodic partner cell, or are
-// computed by the edge lane for transmissive faces.  Faces linked to other
-// sub-blocks (halo padding) are not handled here: such grids use the
-// separate kernels.
+// Tile = (R whole x rows at consecutive z) x (segment of p.seg rows along
+// y).  A row takes P lanes: one per cell (P = n0), or, when an x face is
+// linked to a sub-block, one per padded position x = -2 .. n0+1 (P = n0 + 4)
+// so that the four ghost lanes load the padding the halo copy filled.
+// Otherwise the lanes holding cells 0, 1, n0-2, n0-1 also write the ghost
+// slots the boundary condition defines (wrap or clamp).  Per loaded row:
+// publish the cells to LDS; reconstruct and publish each cell's right
+// evolved state; compute each cell's left face flux and publish it; update.
+// The ghost reconstruction and the right-most face come from the periodic
+// partner cell, or are computed by the edge lane otherwise.
+//
+// Rows outside the grid along y are the mapped interior rows (periodic,
+// transmissive) or the padding rows of a linked face, which hold the
+// neighbour's state before this pass (and, at their x ends, the diagonal
+// neighbour's: the x halo copy that precedes this pass covers the y padding
+// rows); the pass x-sweeps them like any other row.
 //
 // Rings (period 3): raw rows are loaded three iterations before they are
 // x-swept; x-swept rows j, j+1, j+2 are held while cell j is updated.
+//
 // Iterations per trip of the marching loop, a multiple of the ring period 3.
 // Loads issued in an earlier trip are waited for at a trip's first use (the
 // wait counter is merged conservatively at the loop head), so longer trips
@@ -373,12 +380,14 @@ template <typename T> constexpr int xy_unroll() {
   return sizeof(T) == 4 ? RFV_XY_UNROLL_F32 : RFV_XY_UNROLL_F64;
 }
 
-template <typename T, int LAY, int CX, int NT>
-__global__ void __launch_bounds__(NT) k_sweep_xy(SweepParams p, const DevGrid* __restrict__ grids,
-                                                 const int64_t* __restrict__ tile_start,
-                                                 const double* __restrict__ lamv) {
-  // LDS slots per component: R rows of nx + 4 with nx >= XY_MIN_NX
-  constexpr int LN = NT * CX + 4 * (NT * CX / XY_MIN_NX);
+template <typename T, int LAY>
+__global__ void __launch_bounds__(XY_THREADS) k_sweep_xy(SweepParams p,
+                                                         const DevGrid* __restrict__ grids,
+                                                         const int64_t* __restrict__ tile_start,
+                                                         const double* __restrict__ lamv) {
+  constexpr int NT = XY_THREADS;
+  // LDS slots per component: R rows of n0 + 4 slots, R <= NT / XY_MIN_NX
+  constexpr int LN = NT + 4 * (NT / XY_MIN_NX);
   __shared__ T sU[5][LN];
   __shared__ T sR[5][LN];
   __shared__ T sF[5][LN];
@@ -389,28 +398,33 @@ __global__ void __launch_bounds__(NT) k_sweep_xy(SweepParams p, const DevGrid* _
     const DevGrid& G = grids[g];
     const int lt = (int)(gt - tile_start[g]);
     const int nx = G.n[0], ny = G.n[1], nz = G.n[2];
-    const int npr = (nx + CX - 1) / CX;           // lane groups per row
-    const int R = NT / npr;                        // rows per tile
+    const bool ghost_lanes = G.mode[0] == FACE_HALO || G.mode[1] == FACE_HALO;
+    const int P = ghost_lanes ? nx + 4 : nx;      // lanes per row
+    const int R = NT / P;                          // rows per tile
     const int nseg = (ny + p.seg - 1) / p.seg;
     const int chunk = lt / nseg;
     const int s = lt - chunk * nseg;
-    const int rs = tid / npr;                      // row slot of this lane
-    const int i0 = (tid - rs * npr) * CX;
+    const int rs = tid / P;                        // row slot of this lane
+    const int x = tid - rs * P - (ghost_lanes ? 2 : 0);  // the lane's x (-2 .. n0+1)
     const int kk = chunk * R + rs;
-    const bool on = rs < R && kk < nz;             // the lane owns cells
-    bool has[CX];
-#pragma unroll
-    for (int m = 0; m < CX; ++m) has[m] = on && i0 + m < nx;
-    const int nlast = min(CX, nx - i0);            // cells the lane owns (if on)
-    const bool periodic_x = G.mode[0] == FACE_PERIODIC;
+    const bool row_on = rs < R && kk < nz;         // the lane belongs to a row
+    const bool on = row_on && x >= 0 && x < nx;    // ... and holds an interior cell
+    // both x faces periodic: the ghost reconstruction and the last face are
+    // those of the partner cells (any other case computes them)
+    const bool periodic_x = G.mode[0] == FACE_PERIODIC && G.mode[1] == FACE_PERIODIC;
     const int LP = nx + 4;                         // LDS row pitch
-    const int lb = (on ? rs : 0) * LP + 2;         // LDS slot of cell 0 of the lane's row
-    // addresses: column (i0, kk) at row j is q0 + (j + 2) Px + lane offset
-    const int kc = on ? kk : chunk * R;
-    const int ic = on ? i0 : 0;
-    const int64_t qlane = (int64_t)(kc + 2) * G.pxy + (ic + G.ox);
+    const int lb = (row_on ? rs : 0) * LP + 2;     // LDS slot of cell 0 of the lane's row
+    const int xl = row_on ? x : 0;                 // LDS slot the lane writes: lb + xl
+    const int xr = on ? x : 0;                     // slot whose neighbours it reads
+    // addresses: column (x, kk) at row j is q0 + (j + 2) Px + lane offset; a
+    // ghost lane reads the cell its face names (clamped, wrapped or padding)
+    const int kc = row_on ? kk : chunk * R;
+    const int xc = row_on ? face_index(x, nx, G.mode[0], G.mode[1]) : 0;
+    const int64_t qlane = (int64_t)(kc + 2) * G.pxy + (xc + G.ox);
     const int64_t q0 = uniform(((int64_t)(chunk * R + 2) * G.pxy + G.ox) & ~int64_t(63));
     const uint32_t lane = Layout<LAY>::rel((uint32_t)(qlane - q0)) * (uint32_t)sizeof(T);
+    const uint32_t lane_st =
+        Layout<LAY>::rel((uint32_t)(qlane - q0 + (x - xc))) * (uint32_t)sizeof(T);
     const int mlo = G.mode[2], mhi = G.mode[3];
     const void* src = G.buf[p.in];
     void* dst = G.buf[p.out];
@@ -427,71 +441,59 @@ __global__ void __launch_bounds__(NT) k_sweep_xy(SweepParams p, const DevGrid* _
       return q0 + (int64_t)(face_index(min(j, jlast), ny, mlo, mhi) + 2) * G.px;
     };
 
-    // x sweep of one row held by the lanes: u (inputs) -> o (x-swept)
-    auto xsweep = [&](const T u[CX][5], T o[CX][5]) __attribute__((always_inline)) {
+    // x sweep of one row held by the lanes: u (this lane's cell) -> o
+    auto xsweep = [&](const T u[5], T o[5]) __attribute__((always_inline)) {
+      if (row_on && (on || ghost_lanes)) {
 #pragma unroll
-      for (int m = 0; m < CX; ++m) {
-        if (has[m]) {
-          const int i = i0 + m;
-#pragma unroll
-          for (int c = 0; c < 5; ++c) sU[c][lb + i] = u[m][c];
+        for (int c = 0; c < 5; ++c) sU[c][lb + xl] = u[c];
+        if (on && !ghost_lanes) {
           if (periodic_x) {
-            if (i >= nx - 2) {
+            if (x >= nx - 2) {
 #pragma unroll
-              for (int c = 0; c < 5; ++c) sU[c][lb + i - nx] = u[m][c];
+              for (int c = 0; c < 5; ++c) sU[c][lb + x - nx] = u[c];
             }
-            if (i < 2) {
+            if (x < 2) {
 #pragma unroll
-              for (int c = 0; c < 5; ++c) sU[c][lb + nx + i] = u[m][c];
+              for (int c = 0; c < 5; ++c) sU[c][lb + nx + x] = u[c];
             }
           } else {
-            if (i == 0) {
+            if (x == 0) {
 #pragma unroll
-              for (int c = 0; c < 5; ++c) sU[c][lb - 1] = sU[c][lb - 2] = u[m][c];
+              for (int c = 0; c < 5; ++c) sU[c][lb - 1] = sU[c][lb - 2] = u[c];
             }
-            if (i == nx - 1) {
+            if (x == nx - 1) {
 #pragma unroll
-              for (int c = 0; c < 5; ++c) sU[c][lb + nx] = sU[c][lb + nx + 1] = u[m][c];
+              for (int c = 0; c < 5; ++c) sU[c][lb + nx] = sU[c][lb + nx + 1] = u[c];
             }
           }
         }
       }
       __syncthreads();
-      T bl[CX][5], br[CX][5];
-#pragma unroll
-      for (int m = 0; m < CX; ++m) {
+      T bl[5], br[5];
+      {
         T dm[5], dp[5];
-        const int i = i0 + m;
 #pragma unroll
         for (int c = 0; c < 5; ++c) {
-          const T um = m > 0 ? u[m - 1][c] : sU[c][lb + i - 1];
-          const T up = (m + 1 < CX && m + 1 < nlast) ? u[m + 1][c] : sU[c][lb + i + 1];
-          dm[c] = u[m][c] - um;
-          dp[c] = up - u[m][c];
+          dm[c] = u[c] - sU[c][lb + xr - 1];
+          dp[c] = sU[c][lb + xr + 1] - u[c];
         }
-        hancock<T, 0>(u[m], dm, dp, hlx, bl[m], br[m]);
+        hancock<T, 0>(u, dm, dp, hlx, bl, br);
       }
       if (on) {
-        const int ml = nlast - 1;
 #pragma unroll
-        for (int m = 0; m < CX; ++m) {
-          if (m == ml) {
+        for (int c = 0; c < 5; ++c) sR[c][lb + x] = br[c];
+        if (periodic_x && x == nx - 1) {
 #pragma unroll
-            for (int c = 0; c < 5; ++c) sR[c][lb + i0 + m] = br[m][c];
-            if (periodic_x && i0 + m == nx - 1) {
-#pragma unroll
-              for (int c = 0; c < 5; ++c) sR[c][lb - 1] = br[m][c];
-            }
-          }
+          for (int c = 0; c < 5; ++c) sR[c][lb - 1] = br[c];
         }
-        if (!periodic_x && i0 == 0) {
+        if (!periodic_x && x == 0) {
           // ghost cell -1: stencil u_{-2}, u_{-1}, u_0
           T ug[5], dm[5], dp[5], gl[5], gr[5];
 #pragma unroll
           for (int c = 0; c < 5; ++c) {
             ug[c] = sU[c][lb - 1];
             dm[c] = ug[c] - sU[c][lb - 2];
-            dp[c] = u[0][c] - ug[c];
+            dp[c] = u[c] - ug[c];
           }
           hancock<T, 0>(ug, dm, dp, hlx, gl, gr);
 #pragma unroll
@@ -499,91 +501,72 @@ __global__ void __launch_bounds__(NT) k_sweep_xy(SweepParams p, const DevGrid* _
         }
       }
       __syncthreads();
-      T fl[CX][5];
-#pragma unroll
-      for (int m = 0; m < CX; ++m) {
+      T fl[5];
+      {
         T left[5];
 #pragma unroll
-        for (int c = 0; c < 5; ++c) left[c] = m > 0 ? br[m - 1][c] : sR[c][lb + i0 - 1];
-        hllc<T, 0>(left, bl[m], fl[m]);                 // face i0 + m - 1/2
+        for (int c = 0; c < 5; ++c) left[c] = sR[c][lb + xr - 1];
+        hllc<T, 0>(left, bl, fl);                        // face x - 1/2
       }
       if (on) {
 #pragma unroll
-        for (int c = 0; c < 5; ++c) sF[c][lb + i0] = fl[0][c];
+        for (int c = 0; c < 5; ++c) sF[c][lb + x] = fl[c];
         if (periodic_x) {
-          if (i0 == 0) {
+          if (x == 0) {
 #pragma unroll
-            for (int c = 0; c < 5; ++c) sF[c][lb + nx] = fl[0][c];
+            for (int c = 0; c < 5; ++c) sF[c][lb + nx] = fl[c];
           }
-        } else if (i0 + nlast == nx) {
-          // ghost cell nx: stencil u_{nx-1}, u_nx, u_{nx+1}; face nx - 1/2
-          const int ml = nlast - 1;
-          T ue[5], ug[5], dm[5], dp[5], gl[5], gr[5], fg[5];
+        } else if (x == nx - 1) {
+          // ghost cell n0: stencil u_{n0-1}, u_{n0}, u_{n0+1}; face n0 - 1/2
+          T ug[5], dm[5], dp[5], gl[5], gr[5], fg[5];
 #pragma unroll
-          for (int m = 0; m < CX; ++m) {
-            if (m == ml) {
-#pragma unroll
-              for (int c = 0; c < 5; ++c) ue[c] = br[m][c];
-#pragma unroll
-              for (int c = 0; c < 5; ++c) {
-                ug[c] = sU[c][lb + nx];
-                dm[c] = ug[c] - u[m][c];
-                dp[c] = sU[c][lb + nx + 1] - ug[c];
-              }
-            }
+          for (int c = 0; c < 5; ++c) {
+            ug[c] = sU[c][lb + nx];
+            dm[c] = ug[c] - u[c];
+            dp[c] = sU[c][lb + nx + 1] - ug[c];
           }
           hancock<T, 0>(ug, dm, dp, hlx, gl, gr);
-          hllc<T, 0>(ue, gl, fg);
+          hllc<T, 0>(br, gl, fg);
 #pragma unroll
           for (int c = 0; c < 5; ++c) sF[c][lb + nx] = fg[c];
         }
       }
       __syncthreads();
+      T fp[5];
 #pragma unroll
-      for (int m = 0; m < CX; ++m) {
-        T fp[5];
-#pragma unroll
-        for (int c = 0; c < 5; ++c)
-          fp[c] = (m + 1 < CX && m + 1 < nlast) ? fl[m + 1][c] : sF[c][lb + i0 + m + 1];
-        update(u[m], lamx, fp, fl[m], o[m]);
-      }
+      for (int c = 0; c < 5; ++c) fp[c] = sF[c][lb + xr + 1];
+      update(u, lamx, fp, fl, o);
     };
 
     // raw ring slot of row r and x-swept ring slot: (r - (j0 - 2)) mod 3
-    T raw[3][CX][5];
-    T xs[3][CX][5];
-    T dprev[CX][5], dnext[5], bl[5], br[CX][5], brp[CX][5], fprev[CX][5];
+    T raw[3][5];
+    T xs[3][5];
+    T dprev[5], dnext[5], bl[5], br[5], brp[5], fprev[5];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) load_group<T, LAY, CX>(src, row(j0 - 2 + k), ptot, lane, raw[k]);
+    for (int k = 0; k < 3; ++k) load_cell_rel<T, LAY>(src, row(j0 - 2 + k), ptot, lane, raw[k]);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       xsweep(raw[k], xs[k]);                                      // rows j0-2, j0-1, j0
-      load_group<T, LAY, CX>(src, row(j0 + 1 + k), ptot, lane, raw[k]);
+      load_cell_rel<T, LAY>(src, row(j0 + 1 + k), ptot, lane, raw[k]);
     }
 #pragma unroll
-    for (int m = 0; m < CX; ++m) {
-#pragma unroll
-      for (int c = 0; c < 5; ++c) {
-        dprev[m][c] = xs[1][m][c] - xs[0][m][c];
-        dnext[c] = xs[2][m][c] - xs[1][m][c];
-      }
-      hancock<T, 1>(xs[1][m], dprev[m], dnext, hly, bl, brp[m]);   // cell j0 - 1
-#pragma unroll
-      for (int c = 0; c < 5; ++c) dprev[m][c] = dnext[c];
+    for (int c = 0; c < 5; ++c) {
+      dprev[c] = xs[1][c] - xs[0][c];
+      dnext[c] = xs[2][c] - xs[1][c];
     }
+    hancock<T, 1>(xs[1], dprev, dnext, hly, bl, brp);              // cell j0 - 1
+#pragma unroll
+    for (int c = 0; c < 5; ++c) dprev[c] = dnext[c];
     xsweep(raw[0], xs[0]);                                          // row j0 + 1
-    load_group<T, LAY, CX>(src, row(j0 + 4), ptot, lane, raw[0]);
+    load_cell_rel<T, LAY>(src, row(j0 + 4), ptot, lane, raw[0]);
 #pragma unroll
-    for (int m = 0; m < CX; ++m) {
+    for (int c = 0; c < 5; ++c) dnext[c] = xs[0][c] - xs[2][c];
+    hancock<T, 1>(xs[2], dprev, dnext, hly, bl, br);                // cell j0
+    hllc<T, 1>(brp, bl, fprev);                                     // face j0 - 1/2
 #pragma unroll
-      for (int c = 0; c < 5; ++c) dnext[c] = xs[0][m][c] - xs[2][m][c];
-      hancock<T, 1>(xs[2][m], dprev[m], dnext, hly, bl, br[m]);    // cell j0
-      hllc<T, 1>(brp[m], bl, fprev[m]);                            // face j0 - 1/2
-#pragma unroll
-      for (int c = 0; c < 5; ++c) {
-        brp[m][c] = br[m][c];
-        dprev[m][c] = dnext[c];
-      }
+    for (int c = 0; c < 5; ++c) {
+      brp[c] = br[c];
+      dprev[c] = dnext[c];
     }
 
     // Iteration o (cell j = j0 + o), k = o mod U: xs[(k+2)%3] = U_j,
@@ -599,28 +582,23 @@ __global__ void __launch_bounds__(NT) k_sweep_xy(SweepParams p, const DevGrid* _
         if (o >= len) break;
         const int j = j0 + o;
         xsweep(raw[(k + 1) % 3], xs[(k + 1) % 3]);                 // row j + 2
-        load_group<T, LAY, CX>(src, row(j + 5), ptot, lane, raw[(k + 1) % 3]);
-        T out[CX][5];
+        load_cell_rel<T, LAY>(src, row(j + 5), ptot, lane, raw[(k + 1) % 3]);
+        const T* uj = xs[(k + 2) % 3];
+        const T* uj1 = xs[k % 3];
+        const T* uj2 = xs[(k + 1) % 3];
 #pragma unroll
-        for (int m = 0; m < CX; ++m) {
-          const T* uj = xs[(k + 2) % 3][m];
-          const T* uj1 = xs[k % 3][m];
-          const T* uj2 = xs[(k + 1) % 3][m];
+        for (int c = 0; c < 5; ++c) dnext[c] = uj2[c] - uj1[c];
+        hancock<T, 1>(uj1, dprev, dnext, hly, bl, br);             // cell j + 1
+        T fcur[5], out[5];
+        hllc<T, 1>(brp, bl, fcur);                                 // face j + 1/2
+        update(uj, lamy, fcur, fprev, out);
 #pragma unroll
-          for (int c = 0; c < 5; ++c) dnext[c] = uj2[c] - uj1[c];
-          hancock<T, 1>(uj1, dprev[m], dnext, hly, bl, br[m]);     // cell j + 1
-          T fcur[5];
-          hllc<T, 1>(brp[m], bl, fcur);                            // face j + 1/2
-          update(uj, lamy, fcur, fprev[m], out[m]);
-#pragma unroll
-          for (int c = 0; c < 5; ++c) {
-            fprev[m][c] = fcur[c];
-            brp[m][c] = br[m][c];
-            dprev[m][c] = dnext[c];
-          }
+        for (int c = 0; c < 5; ++c) {
+          fprev[c] = fcur[c];
+          brp[c] = br[c];
+          dprev[c] = dnext[c];
         }
-        if (has[0])
-          store_group<T, LAY, CX>(dst, q0 + (int64_t)(j + 2) * G.px, ptot, lane, out, has[CX - 1]);
+        if (on) store_cell_rel<T, LAY>(dst, q0 + (int64_t)(j + 2) * G.px, ptot, lane_st, out);
       }
     }
     __syncthreads();
@@ -708,12 +686,16 @@ __global__ void __launch_bounds__(256) k_dt(Work w, double cfl, double fixed_dt,
 // extents, which match between the two sub-blocks) are copied from the
 // source's interior edge into the destination's padding.
 template <typename T, int LAY>
-__global__ void __launch_bounds__(256) k_halo(Work w, int buf, int axis, const HaloTask* tasks) {
+// `ext` extends the first axis across the face by that many padding layers on
+// each side (the x copy that precedes a fused x-y pass also fills the corner
+// cells of the y padding rows, which the y copy filled just before).
+__global__ void __launch_bounds__(256) k_halo(Work w, int buf, int axis, int ext,
+                                              const HaloTask* tasks) {
   const HaloTask tk = tasks[blockIdx.y];
   const DevGrid& Gd = w.grids[tk.dst];
   const DevGrid& Gs = w.grids[tk.src];
   const int a0 = axis == 0 ? 1 : 0, a1 = axis == 2 ? 1 : 2;  // axes across
-  const uint32_t na = a0 == 0 ? Gd.n[0] : Gd.n[1];
+  const uint32_t na = (a0 == 0 ? Gd.n[0] : Gd.n[1]) + 2 * ext;
   const uint32_t nb = a1 == 1 ? Gd.n[1] : Gd.n[2];
   const uint32_t area = na * nb;
   const int64_t d_a0 = a0 == 1 ? Gd.px : 1, d_a1 = a1 == 1 ? Gd.px : Gd.pxy;
@@ -728,7 +710,8 @@ __global__ void __launch_bounds__(256) k_halo(Work w, int buf, int axis, const H
   for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < 2 * area;
        e += gridDim.x * blockDim.x) {
     const uint32_t layer = e / area, r = e - layer * area;
-    const uint32_t ia = r % na, ib = r / na;
+    const int ia = (int)(r % na) - ext;
+    const uint32_t ib = r / na;
     // index along the axis: destination padding, source interior edge
     const int dpos = (tk.side == 0 ? (int)layer - 2 : nd + (int)layer) + d_o;
     const int spos = (tk.side == 0 ? ns - 2 + (int)layer : (int)layer) + s_o;
@@ -926,13 +909,18 @@ int64_t tiles_yz(const ripple_fv_grid& g, int axis, int yz_block, int yz_segment
   return nchunk * nseg;
 }
 
-bool xy_eligible(const ripple_fv_grid& g, int cols) {
-  return g.n[0] >= XY_MIN_NX && (g.n[0] + cols - 1) / cols <= xy_threads(cols) && g.nbr[0] < 0 &&
-         g.nbr[1] < 0 && g.nbr[2] < 0 && g.nbr[3] < 0;
+// Lanes per x row in the fused sweep: one per cell, or one per padded
+// position when an x face is linked to a sub-block.
+static int xy_row_lanes(const ripple_fv_grid& g) {
+  return (g.nbr[0] >= 0 || g.nbr[1] >= 0) ? g.n[0] + 4 : g.n[0];
 }
 
-int64_t tiles_xy(const ripple_fv_grid& g, int yz_segment, int cols) {
-  const int64_t rows = xy_threads(cols) / ((g.n[0] + cols - 1) / cols);
+bool xy_eligible(const ripple_fv_grid& g) {
+  return g.n[0] >= XY_MIN_NX && xy_row_lanes(g) <= XY_THREADS;
+}
+
+int64_t tiles_xy(const ripple_fv_grid& g, int yz_segment) {
+  const int64_t rows = XY_THREADS / xy_row_lanes(g);
   const int64_t nchunk = (g.n[2] + rows - 1) / rows;
   const int64_t nseg = (g.n[1] + yz_segment - 1) / yz_segment;
   return nchunk * nseg;
@@ -1001,10 +989,8 @@ hipError_t launch_sweep(int dtype, int lay, int axis, const Tiling& tl, const Sw
 
 template <typename T, int LAY>
 static hipError_t sweep_xy_typed(const Tiling&, const SweepParams& p, int blocks, hipStream_t s) {
-  // one cell per thread: with two, the deep unroll that hides the memory
-  // latency no longer fits the register file (and was slower when it did)
-  hipLaunchKernelGGL((k_sweep_xy<T, LAY, 1, xy_threads(1)>), dim3(blocks), dim3(xy_threads(1)), 0, s,
-                     p, p.w.grids, p.tiles.tile_start, p.w.lam);
+  hipLaunchKernelGGL((k_sweep_xy<T, LAY>), dim3(blocks), dim3(XY_THREADS), 0, s, p, p.w.grids,
+                     p.tiles.tile_start, p.w.lam);
   return hipGetLastError();
 }
 
@@ -1054,26 +1040,26 @@ hipError_t launch_dt(const Work& w, double cfl, double fixed_dt, int reset_s, do
 }
 
 template <typename T>
-static hipError_t halo_lay(int lay, const Work& w, int buf, int axis, const HaloTask* tasks,
-                           dim3 grid, hipStream_t s) {
+static hipError_t halo_lay(int lay, const Work& w, int buf, int axis, int ext,
+                           const HaloTask* tasks, dim3 grid, hipStream_t s) {
   switch (lay) {
-    case LAY_AOS: hipLaunchKernelGGL((k_halo<T, LAY_AOS>), grid, dim3(256), 0, s, w, buf, axis, tasks); break;
-    case LAY_SOA: hipLaunchKernelGGL((k_halo<T, LAY_SOA>), grid, dim3(256), 0, s, w, buf, axis, tasks); break;
-    case LAY_AOSOA16: hipLaunchKernelGGL((k_halo<T, LAY_AOSOA16>), grid, dim3(256), 0, s, w, buf, axis, tasks); break;
-    case LAY_AOSOA32: hipLaunchKernelGGL((k_halo<T, LAY_AOSOA32>), grid, dim3(256), 0, s, w, buf, axis, tasks); break;
-    default: hipLaunchKernelGGL((k_halo<T, LAY_AOSOA64>), grid, dim3(256), 0, s, w, buf, axis, tasks); break;
+    case LAY_AOS: hipLaunchKernelGGL((k_halo<T, LAY_AOS>), grid, dim3(256), 0, s, w, buf, axis, ext, tasks); break;
+    case LAY_SOA: hipLaunchKernelGGL((k_halo<T, LAY_SOA>), grid, dim3(256), 0, s, w, buf, axis, ext, tasks); break;
+    case LAY_AOSOA16: hipLaunchKernelGGL((k_halo<T, LAY_AOSOA16>), grid, dim3(256), 0, s, w, buf, axis, ext, tasks); break;
+    case LAY_AOSOA32: hipLaunchKernelGGL((k_halo<T, LAY_AOSOA32>), grid, dim3(256), 0, s, w, buf, axis, ext, tasks); break;
+    default: hipLaunchKernelGGL((k_halo<T, LAY_AOSOA64>), grid, dim3(256), 0, s, w, buf, axis, ext, tasks); break;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_halo(int dtype, int lay, const Work& w, int buf, int axis, const HaloTask* tasks,
-                       int ntasks, int64_t max_area, hipStream_t s) {
+hipError_t launch_halo(int dtype, int lay, const Work& w, int buf, int axis, int ext,
+                       const HaloTask* tasks, int ntasks, int64_t max_area, hipStream_t s) {
   if (ntasks <= 0) return hipSuccess;
   int64_t bx = (2 * max_area + 255) / 256;
   if (bx > 4096) bx = 4096;
   const dim3 grid((unsigned)bx, (unsigned)ntasks);
-  return dtype == RIPPLE_FV_F32 ? halo_lay<float>(lay, w, buf, axis, tasks, grid, s)
-                                : halo_lay<double>(lay, w, buf, axis, tasks, grid, s);
+  return dtype == RIPPLE_FV_F32 ? halo_lay<float>(lay, w, buf, axis, ext, tasks, grid, s)
+                                : halo_lay<double>(lay, w, buf, axis, ext, tasks, grid, s);
 }
 
 static unsigned fill_blocks(int64_t n) {

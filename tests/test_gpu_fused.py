@@ -1,8 +1,10 @@
 """The fused x-then-y sweep gives bitwise the states of the separate x and y
-sweeps, for every layout, precision, boundary condition and row length;
-grids it does not accept (rows outside 16..512 cells, x or y faces linked to
-sub-blocks) fall back to the separate sweeps with the same results.  Also
-checks the in-place semantics of the step entry points on both paths."""
+sweeps, for every layout, precision, boundary condition and row length, and
+for sub-blocks linked along x and/or y (whose padding, corners included,
+the halo copies fill before the pass); grids it does not accept (rows
+outside 16..512 cells) fall back to the separate sweeps with the same
+results.  Also checks the in-place semantics of the step entry points on
+both paths."""
 import numpy as np
 import pytest
 import torch
@@ -50,16 +52,17 @@ def test_fused_row_lengths(nx):
         assert tf == ts and np.array_equal(Uf, Us), (nx, bc)
 
 
-def test_linked_sub_blocks_fall_back():
-    """Sub-blocks linked to neighbours run the separate sweeps with halo
-    copies and match the whole grid (which runs fused); the fused sweep entry
-    point reports a linked grid unsupported."""
-    shape = (30, 24, 10)
+def test_linked_sub_blocks_match_whole_grid():
+    """Sub-blocks linked along y, along x, and along both (so the fused pass
+    reads corner padding), fused and split, match the whole grid bitwise; the
+    single fused sweep entry point reports a linked grid unsupported."""
+    shape = (40, 24, 10)   # sub-block rows of 20 or 40 cells: fused
     whole = R.make_grid(shape, dtype=R.F64, layout=R.SOA, bc=(1, 0, 1))
     W = ist.smooth_periodic(shape, seed=77)
     (ref,), (t_ref,) = G.run(whole, W, 3)
-    for parts in ((1, 2, 1), (2, 1, 1), (3, 1, 2)):
-        subs = R.ripple_fv_partition(whole, parts)
+    for parts, split in (((1, 2, 1), 0), ((2, 1, 1), 0), ((2, 2, 1), 0), ((2, 3, 2), 0),
+                         ((2, 2, 1), 1)):
+        subs = [R.copy_grid(sb, split_xy=split) for sb in R.ripple_fv_partition(whole, parts)]
         states, origins = [], []
         for idx, sb in enumerate(subs):
             a, b, c = idx % parts[0], (idx // parts[0]) % parts[1], idx // (parts[0] * parts[1])
