@@ -85,8 +85,9 @@ def run_gpu(n, dtype, layout, aosoa_w, steps, warmup, seed, tiling):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = R.ripple_fv_profile(ctx)
-    # same loop replayed as captured hipGraphs
-    R.ripple_fv_run_batch(ctx, [g], pa, pb, 2, 0.9, R.RUN_GRAPH, stream)
+    # same loop replayed as a captured hipGraph (captured by an untimed run
+    # of the same step count)
+    R.ripple_fv_run_batch(ctx, [g], pa, pb, steps, 0.9, R.RUN_GRAPH, stream)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     R.ripple_fv_run_batch(ctx, [g], pa, pb, steps, 0.9, R.RUN_GRAPH, stream)
@@ -130,7 +131,9 @@ def run_batch_workload(steps, warmup):
                       "yz_cols": grids[0].yz_cols, "split_xy": grids[0].split_xy}}
     for name, flags in (("batched_graph", R.RUN_GRAPH), ("batched_eager", R.RUN_EAGER),
                         ("per_grid", R.RUN_PER_GRID)):
-        R.ripple_fv_run_batch(ctx, grids, pa, pb, warmup, 0.9, flags, stream)
+        # warm-up of the same step count (captures the graph in graph mode)
+        R.ripple_fv_run_batch(ctx, grids, pa, pb, steps if flags & R.RUN_GRAPH else warmup, 0.9,
+                              flags, stream)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         R.ripple_fv_run_batch(ctx, grids, pa, pb, steps, 0.9, flags, stream)
@@ -138,6 +141,11 @@ def run_batch_workload(steps, warmup):
         secs = time.perf_counter() - t0
         out[name] = {"gcell_updates_per_s": round(cells * steps / secs / 1e9, 3),
                      "ms_per_step": round(secs / steps * 1e3, 4)}
+    # per-kernel times of the batched launches (HIP events around each launch)
+    R.ripple_fv_profile(ctx)
+    R.ripple_fv_run_batch(ctx, grids, pa, pb, steps, 0.9, R.RUN_PROFILE, stream)
+    torch.cuda.synchronize()
+    out["kernel_ms"] = {k: round(ms / c, 4) for k, (ms, c) in R.ripple_fv_profile(ctx).items() if c}
     out["status"] = R.ripple_fv_check(ctx)
     R.ripple_fv_destroy(ctx)
     return out

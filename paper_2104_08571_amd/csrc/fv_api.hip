@@ -23,6 +23,8 @@ namespace {
 
 constexpr int64_t MAX_BYTES = int64_t(1) << 46;
 constexpr int MAX_PLANS = 16;
+constexpr int GRAPH_MAX_STEPS = 64;  // steps captured in one graph
+constexpr int MAX_GRAPHS = 4;        // cached graphs per plan
 
 struct Plan {
   int n = 0;
@@ -48,13 +50,21 @@ struct Plan {
   hipEvent_t upload_done = nullptr;
   bool upload_pending = false;
   bool uploaded = false;
-  // captured step graphs (one step, two steps) and the cfl they were captured with
-  hipGraphExec_t g1 = nullptr, g2 = nullptr;
+  // captured step loops by step count, and the cfl / launch mode they were
+  // captured with
+  std::map<int, hipGraphExec_t> graphs;
   double graph_cfl = -1.0;
+  bool graph_per_grid = false;
 
+  // (waits for the device first: a launched graph may still be running)
+  void drop_graphs() {
+    if (graphs.empty()) return;
+    hipDeviceSynchronize();
+    for (auto& kv : graphs) hipGraphExecDestroy(kv.second);
+    graphs.clear();
+  }
   ~Plan() {
-    if (g1) hipGraphExecDestroy(g1);
-    if (g2) hipGraphExecDestroy(g2);
+    drop_graphs();
     if (upload_done) {
       hipEventSynchronize(upload_done);
       hipEventDestroy(upload_done);
@@ -677,15 +687,34 @@ ripple_fv_status run(ripple_fv_ctx* ctx, int n, const ripple_fv_grid* grids, voi
     if ((st = enqueue_wavespeed(ctx, P, L, 0, nullptr, per_grid))) return st;
   }
   if ((flags & RIPPLE_FV_RUN_GRAPH) && !(fixed_dt > 0.0) && !dt_out) {
-    if (!P->g1 || P->graph_cfl != cfl) {
-      if (P->g1) { hipGraphExecDestroy(P->g1); P->g1 = nullptr; }
-      if (P->g2) { hipGraphExecDestroy(P->g2); P->g2 = nullptr; }
-      if ((st = capture_graph(ctx, P, 1, cfl, per_grid, &P->g1))) return st;
-      if ((st = capture_graph(ctx, P, 2, cfl, per_grid, &P->g2))) return st;
+    if (P->graph_cfl != cfl || P->graph_per_grid != per_grid) {
+      P->drop_graphs();
       P->graph_cfl = cfl;
+      P->graph_per_grid = per_grid;
     }
-    for (int k = 0; k + 1 < nsteps; k += 2) HIP_OR_FAIL(ctx, hipGraphLaunch(P->g2, s));
-    if (nsteps & 1) HIP_OR_FAIL(ctx, hipGraphLaunch(P->g1, s));
+    // whole step loops of up to GRAPH_MAX_STEPS steps per graph launch (an
+    // even count on the separate-sweep path, whose steps alternate buffers),
+    // then one graph for the remainder; graphs are cached by step count
+    int chunk = std::min(nsteps, GRAPH_MAX_STEPS);
+    if (!P->fused && chunk > 1) chunk &= ~1;
+    auto graph_for = [&](int k, hipGraphExec_t* out) -> ripple_fv_status {
+      auto it = P->graphs.find(k);
+      if (it != P->graphs.end()) {
+        *out = it->second;
+        return RIPPLE_FV_OK;
+      }
+      ripple_fv_status s2 = capture_graph(ctx, P, k, cfl, per_grid, out);
+      if (!s2) P->graphs[k] = *out;
+      return s2;
+    };
+    const int rem = nsteps % chunk;
+    if ((int)P->graphs.size() + 2 > MAX_GRAPHS && (!P->graphs.count(chunk) || (rem && !P->graphs.count(rem))))
+      P->drop_graphs();
+    hipGraphExec_t gc = nullptr, gr = nullptr;
+    if ((st = graph_for(chunk, &gc))) return st;
+    if (rem && (st = graph_for(rem, &gr))) return st;
+    for (int k = 0; k + chunk <= nsteps; k += chunk) HIP_OR_FAIL(ctx, hipGraphLaunch(gc, s));
+    if (rem) HIP_OR_FAIL(ctx, hipGraphLaunch(gr, s));
     // (the copy back stays outside the graphs: its pointers change with the buffers)
     if (!P->fused && (nsteps & 1)) return enqueue_copy_back(ctx, P, s);
     return RIPPLE_FV_OK;
