@@ -134,3 +134,21 @@ def test_fused_batch_graph_replays():
     assert ts == te
     for x, y in zip(outs, eager):
         assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("split", [0, 1])
+def test_graph_step_counts(split):
+    """Graph replays of step loops of any length (one graph of up to 64 steps
+    repeated, plus a remainder graph; cached by step count and launch mode)
+    equal the eager loop, on both the fused and the separate-sweep path."""
+    ext = [(24, 20, 16), (17, 30, 12)]
+    grids = [R.make_grid(e, dtype=R.F32, layout=R.SOA, bc=(1, 1, 1),
+                         tiling=(0, 0, 0, 0, 0, split)) for e in ext]
+    states = [ist.smooth_periodic(e, seed=90 + i) for i, e in enumerate(ext)]
+    for n in (1, 2, 3, 7, 67, 3):
+        eager, te = G.run(grids, states, n)
+        for flags in (R.RUN_GRAPH, R.RUN_GRAPH | R.RUN_PER_GRID):
+            outs, ts = G.run(grids, states, n, flags=flags)
+            assert ts == te, (n, flags)
+            for x, y in zip(outs, eager):
+                assert np.array_equal(x, y), (n, flags)
