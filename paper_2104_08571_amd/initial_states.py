@@ -6,10 +6,12 @@ arithmetic (no equation of state, flux or update); both the FP64 oracle and
 the HIP library convert the primitive fields it returns to conserved
 variables with their own code.
 
-Every generator returns a float64 torch tensor ``[5, nz, ny, nx]`` holding
-(rho, u, v, w, p) at cell centres x_c = (i + 1/2) / N of the unit cube, on
-the requested device.  Sub-blocks of a larger grid are produced by passing
-the global extents and the block's origin.
+Every three-dimensional generator returns a float64 torch tensor
+``[5, nz, ny, nx]`` holding (rho, u, v, w, p) at cell centres
+x_c = (i + 1/2) / N of the unit cube, on the requested device; the ``_2d``
+generators return ``[4, ny, nx]`` holding (rho, u, v, p) on the unit square.
+Sub-blocks of a larger grid are produced by passing the global extents and
+the block's origin.
 
 Random numbers come from SplitMix64 (Steele, Lea and Flood, "Fast splittable
 pseudorandom number generators", OOPSLA 2014), uniform u = (x >> 11) * 2^-53.
@@ -172,6 +174,81 @@ def random_physical(n, seed, device="cpu", spread=0.25, speed=0.3):
     W[1:4] = speed * (2.0 * vals[1:4] - 1.0)
     W[4] = 1.0 - spread + 2.0 * spread * vals[4]
     return W.to(device)
+
+
+# Two-dimensional states for the flux-difference workload: float64
+# [4, ny, nx] holding (rho, u, v, p) at cell centres of the unit square.
+
+def fourier_modes_2d(rng, count=N_MODES):
+    """`count` modes (kx, ky, a, phi) drawn in that order: wavenumbers
+    integers in 1..4, amplitudes U(0,1), phases U(0, 2 pi)."""
+    modes = []
+    for _ in range(count):
+        kx = 1 + int(4.0 * rng.uniform())
+        ky = 1 + int(4.0 * rng.uniform())
+        a = rng.uniform()
+        phi = 2.0 * math.pi * rng.uniform()
+        modes.append((kx, ky, a, phi))
+    return modes
+
+
+def fourier_field_2d(modes, x, y):
+    """f = sum_m (a_m / sum a) cos(2 pi (kx x + ky y) + phi_m), [ny, nx]."""
+    total = sum(m[2] for m in modes)
+    f = torch.zeros((y.numel(), x.numel()), dtype=torch.float64, device=x.device)
+    two_pi = 2.0 * math.pi
+    for kx, ky, a, phi in modes:
+        # cos(A + B) = cos A cos B - sin A sin B with A along y, B along x:
+        # two outer products instead of a cosine per cell
+        A = two_pi * ky * y + phi
+        B = two_pi * kx * x
+        f.addr_(torch.cos(A), torch.cos(B), alpha=a / total)
+        f.addr_(torch.sin(A), torch.sin(B), alpha=-a / total)
+    return f
+
+
+def smooth_periodic_2d(n, seed, device="cpu"):
+    """Smooth periodic 2D state on an n = (nx, ny) grid: rho = 1 + 0.2 f_rho,
+    (u, v) = 0.1 (f_u, f_v), p = 1; three independent 8-mode Fourier fields
+    drawn in the order rho, u, v from one SplitMix64 stream."""
+    nx, ny = int(n[0]), int(n[1])
+    rng = SplitMix64(seed)
+    modes = [fourier_modes_2d(rng) for _ in range(3)]
+    x = _centres(nx, 0, nx, device)
+    y = _centres(ny, 0, ny, device)
+    W = torch.empty((4, ny, nx), dtype=torch.float64, device=device)
+    W[0] = fourier_field_2d(modes[0], x, y).mul_(0.2).add_(1.0)
+    W[1] = fourier_field_2d(modes[1], x, y).mul_(0.1)
+    W[2] = fourier_field_2d(modes[2], x, y).mul_(0.1)
+    W[3] = 1.0
+    return W
+
+
+def random_physical_2d(n, seed, device="cpu", spread=0.25, speed=0.3):
+    """Cell-wise independent random 2D states: rho and p uniform in
+    [1 - spread, 1 + spread), velocities uniform in [-speed, speed)."""
+    nx, ny = int(n[0]), int(n[1])
+    rng = SplitMix64(seed)
+    vals = torch.tensor([rng.uniform() for _ in range(4 * nx * ny)], dtype=torch.float64)
+    vals = vals.reshape(4, ny, nx)
+    W = torch.empty_like(vals)
+    W[0] = 1.0 - spread + 2.0 * spread * vals[0]
+    W[1:3] = speed * (2.0 * vals[1:3] - 1.0)
+    W[3] = 1.0 - spread + 2.0 * spread * vals[3]
+    return W.to(device)
+
+
+def sod_2d(n, axis=0, device="cpu", left=(1.0, 0.0, 1.0), right=(0.125, 0.0, 0.1), x0=0.5):
+    """Planar Riemann problem along `axis` (0 = x, 1 = y) on an n = (nx, ny)
+    grid: left = (rho, normal velocity, p) where the cell centre < x0."""
+    nx, ny = int(n[0]), int(n[1])
+    c = _centres((nx, ny)[axis], 0, (nx, ny)[axis], device)
+    is_left = (c < x0).reshape((1, nx) if axis == 0 else (ny, 1)).expand(ny, nx)
+    W = torch.zeros((4, ny, nx), dtype=torch.float64, device=device)
+    W[0] = torch.where(is_left, _f64(left[0], device), _f64(right[0], device))
+    W[1 + axis] = torch.where(is_left, _f64(left[1], device), _f64(right[1], device))
+    W[3] = torch.where(is_left, _f64(left[2], device), _f64(right[2], device))
+    return W
 
 
 def batch_extents(count=64, seed=42, choices=tuple(range(32, 193, 16))):
