@@ -10,7 +10,9 @@ Prints one JSON line.  `value` is Gcell-updates/s at FP32; `roofline` is the
 dominant sweep kernel's algorithmic bytes per launch over its mean launch
 duration, timed with HIP events around every launch inside the timed region;
 `cpu_baseline` times the FP64 CPU oracle on a bounded sample of the same
-workload on this host.
+workload on this host.  `force2d_flux_difference` reports the 2D FORCE
+flux-difference benchmark (square grids of 1024^2 .. 32768^2 cells, FP32 and
+FP64, strided and contiguous layouts), one computation per call.
 """
 import argparse
 import hashlib
@@ -193,6 +195,92 @@ def run_partition_workload(steps, warmup):
     return out
 
 
+# The paper's table of the 2D flux difference ("tab:flux", one V100, ms per
+# computation) for the strided and contiguous layouts -- other hardware,
+# reported as context only.
+PAPER_FLUX_MS = {"soa": {1024: 0.0757, 2048: 0.2438, 4096: 0.9101, 8192: 3.5533,
+                         16384: 14.282, 32768: 59.028},
+                 "aos": {1024: 0.1065, 2048: 0.3614, 4096: 1.3971, 8192: 5.5284,
+                         16384: 22.081, 32768: 86.756}}
+# Arithmetic of one cell of the 2D flux difference, counted like the sweeps'
+# (each face flux is evaluated once and shared by its two cells): physical
+# x and y fluxes of the cell 19, one x and one y FORCE face 2 x 62, the two
+# differences and their sum 12.
+FLOPS_PER_CELL_FORCE2D = 155
+
+
+def run_force2d_workload(sizes, dtypes, layouts, reps, warmup):
+    """2D FORCE flux difference (one computation = every cell's D) on square
+    smooth periodic grids: mean and minimum time per computation from HIP
+    events around every call on the launching stream, with the state
+    resident in HBM."""
+    import torch
+
+    from paper_2104_08571_amd import initial_states as ist
+    from paper_2104_08571_amd import ripple_fv as R
+
+    ctx = R.ripple_fv_create(0)
+    stream = torch.cuda.current_stream()
+    lays = {"soa": (R.SOA, 0), "aos": (R.AOS, 0), "aosoa64": (R.AOSOA, 64)}
+    lam = 0.25
+    rows = []
+    try:
+        for dt_name in dtypes:
+            dtype = R.F32 if dt_name == "f32" else R.F64
+            s_bytes = 4 if dtype == R.F32 else 8
+            for lay_name in layouts:
+                for n in sizes:
+                    g = R.make_force2d_grid((n, n), dtype=dtype, layout=lays[lay_name][0],
+                                            aosoa_w=lays[lay_name][1], bc=(R.PERIODIC,) * 2)
+                    u = torch.empty(g.bytes, dtype=torch.uint8, device="cuda")
+                    d = torch.empty(g.bytes, dtype=torch.uint8, device="cuda")
+                    W = ist.smooth_periodic_2d((n, n), 2104, device="cuda")
+                    R.ripple_force2d_import(ctx, g, W.data_ptr(), R.PRIMITIVE, u.data_ptr(),
+                                            stream.cuda_stream)
+                    torch.cuda.synchronize()
+                    del W
+                    for _ in range(warmup):
+                        R.ripple_force2d_flux_difference(ctx, g, u.data_ptr(), lam, lam,
+                                                         d.data_ptr(), stream.cuda_stream)
+                    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+                    torch.cuda.synchronize()
+                    ev[0].record(stream)
+                    for k in range(reps):
+                        R.ripple_force2d_flux_difference(ctx, g, u.data_ptr(), lam, lam,
+                                                         d.data_ptr(), stream.cuda_stream)
+                        ev[k + 1].record(stream)
+                    torch.cuda.synchronize()
+                    ms = [ev[k].elapsed_time(ev[k + 1]) for k in range(reps)]
+                    mean = sum(ms) / reps
+                    cells = n * n
+                    row = {"n": n, "dtype": dt_name, "layout": lay_name,
+                           "ms": round(mean, 4), "ms_min": round(min(ms), 4),
+                           "gcells_per_s": round(cells / mean / 1e6, 2),
+                           "GBps_algorithmic": round(8 * s_bytes * cells / mean / 1e6, 1)}
+                    if lay_name in PAPER_FLUX_MS and n in PAPER_FLUX_MS[lay_name]:
+                        row["paper_v100_ms"] = PAPER_FLUX_MS[lay_name][n]
+                    rows.append(row)
+                    print(f"[bench] force2d {dt_name} {lay_name} {n}^2: {row}", file=sys.stderr,
+                          flush=True)
+                    del u, d
+                    torch.cuda.empty_cache()
+    finally:
+        R.ripple_fv_destroy(ctx)
+    out = {"workload": "flux_difference_2d_smooth_periodic", "lam": lam, "reps": reps,
+           "results": rows}
+    big = [r for r in rows if r["layout"] == "soa" and r["n"] == max(sizes)]
+    for r in big:
+        gbs = r["GBps_algorithmic"]
+        key = f"flux_difference_2d_{r['n']}sq_{r['dtype']}_soa"
+        out[f"roofline_{r['dtype']}"] = {
+            "bound": "hbm", "kernel": "force2d", "workload": key, "achieved": gbs,
+            "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4),
+            "traffic": measured_traffic("force2d", key), "mean_launch_ms": r["ms"],
+            "bytes_per_launch_algorithmic": 8 * (4 if r["dtype"] == "f32" else 8) * r["n"] ** 2,
+            "tflops_algorithmic": round(FLOPS_PER_CELL_FORCE2D * r["n"] ** 2 / r["ms"] / 1e9, 2)}
+    return out
+
+
 def copy_ceiling(nbytes=2 << 30, reps=20):
     """Device-to-device copy rate of a plain copy kernel (torch's) over
     `nbytes`-byte buffers: (read + write bytes) / time.  It is the practical
@@ -273,6 +361,13 @@ def main():
                     help="oracle steps timed for cpu_baseline (0 = skip)")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the batched and partitioned workloads")
+    ap.add_argument("--no-force2d", action="store_true",
+                    help="skip the 2D FORCE flux-difference leg")
+    ap.add_argument("--force2d-only", action="store_true",
+                    help="run only the 2D FORCE flux-difference leg (prints its JSON)")
+    ap.add_argument("--force2d-sizes", default="1024,2048,4096,8192,16384,32768")
+    ap.add_argument("--force2d-layouts", default="soa,aos")
+    ap.add_argument("--force2d-dtypes", default="f32,f64")
     ap.add_argument("--copy-only", action="store_true",
                     help="only run the plain-copy calibration (2 GiB, 20 copies) and print it")
     args = ap.parse_args()
@@ -283,6 +378,11 @@ def main():
 
     if args.copy_only:
         print(json.dumps({"copy_ceiling": copy_ceiling()}), flush=True)
+        return
+    f2_args = ([int(v) for v in args.force2d_sizes.split(",")], args.force2d_dtypes.split(","),
+               args.force2d_layouts.split(","), max(args.steps, 5), args.warmup)
+    if args.force2d_only:
+        print(json.dumps({"force2d_flux_difference": run_force2d_workload(*f2_args)}), flush=True)
         return
 
     from paper_2104_08571_amd import ripple_fv as R
@@ -337,6 +437,10 @@ def main():
         part = run_partition_workload(args.steps, args.warmup)
         print(f"[bench] partition 768^3: {part}", file=sys.stderr, flush=True)
 
+    f2 = None
+    if not args.no_force2d:
+        f2 = run_force2d_workload(*f2_args)
+
     base = None
     if args.cpu_steps > 0:
         base = cpu_baseline(n, seed, args.cpu_steps)
@@ -379,6 +483,8 @@ def main():
         out["batch_64_grids_f32"] = batch
     if part is not None:
         out["partition_768_f32_2x2x2"] = part
+    if f2 is not None:
+        out["force2d_flux_difference"] = f2
     print(json.dumps(out), flush=True)
 
 

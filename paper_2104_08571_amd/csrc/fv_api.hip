@@ -729,6 +729,21 @@ ripple_fv_status run(ripple_fv_ctx* ctx, int n, const ripple_fv_grid* grids, voi
 
 }  // namespace
 
+namespace rfv {
+
+ripple_fv_status ctx_begin(ripple_fv_ctx* ctx) { return set_device(ctx); }
+
+ripple_fv_status ctx_fail(ripple_fv_ctx* ctx, ripple_fv_status st, const char* msg) {
+  return fail(ctx, st, msg);
+}
+
+ripple_fv_status ctx_ptr_ok(ripple_fv_ctx* ctx, const void* p, int64_t bytes, int64_t align,
+                            const char* what) {
+  return ptr_ok(ctx, p, bytes, align, what);
+}
+
+}  // namespace rfv
+
 // ===========================================================================
 // C ABI
 // ===========================================================================

@@ -65,4 +65,12 @@ RFV_HD XPos x_position(int tid, int F0, int lx, int ny, int nz) {
   return r;
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs.  Renumber them so
+// that each XCD takes one contiguous run of tiles: neighbouring tiles share
+// halo cells and then share that XCD's L2.
+RFV_HD int64_t xcd_order(int64_t b, int64_t nblocks) {
+  const int64_t x = b & 7, k = b >> 3, q = nblocks >> 3, r = nblocks & 7;
+  return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
 }  // namespace rfv

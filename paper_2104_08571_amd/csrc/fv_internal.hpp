@@ -119,6 +119,14 @@ hipError_t launch_tune_state(double* W, const int n[3], hipStream_t s);
 hipError_t launch_sums(const Desc& d, double* partials, int nblocks, double* out, hipStream_t s);
 hipError_t launch_norms(const Desc& d, const double* ref, double* partials, int nblocks,
                         double* out, hipStream_t s);
+// Context services for entry points outside the step's translation unit:
+// select the context's device and clear its error text; record an error;
+// check that a device pointer is aligned and covers `bytes`.
+ripple_fv_status ctx_begin(ripple_fv_ctx* ctx);
+ripple_fv_status ctx_fail(ripple_fv_ctx* ctx, ripple_fv_status st, const char* msg);
+ripple_fv_status ctx_ptr_ok(ripple_fv_ctx* ctx, const void* p, int64_t bytes, int64_t align,
+                            const char* what);
+
 constexpr int DIAG_BLOCK = 256;
 constexpr int DIAG_MAX_BLOCKS = 1024;
 

@@ -33,14 +33,6 @@ namespace rfv {
 // Tile bookkeeping
 // ---------------------------------------------------------------------------
 
-// Workgroups are dispatched round-robin over the 8 XCDs.  Renumber them so
-// that each XCD takes one contiguous run of tiles: neighbouring tiles share
-// halo cells and then share that XCD's L2.
-__device__ __forceinline__ int64_t xcd_order(int64_t b, int64_t nblocks) {
-  const int64_t x = b & 7, k = b >> 3, q = nblocks >> 3, r = nblocks & 7;
-  return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
-}
-
 // Grid owning global tile t: the last g with tile_start[g] <= t.
 __device__ __forceinline__ int find_grid(const int64_t* start, int n, int64_t t) {
   int lo = 0, hi = n - 1;

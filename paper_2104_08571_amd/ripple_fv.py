@@ -1,4 +1,5 @@
-"""ctypes binding of libripple_fv.so (declared in include/ripple_fv.h).
+"""ctypes binding of libripple_fv.so (declared in include/ripple_fv.h and
+include/ripple_force2d.h).
 
 Argument marshalling only: every computation runs in the HIP library.  The
 functions keep the C names; each raises RippleFVError on a non-OK status
@@ -34,7 +35,13 @@ EXPORTED = [
     "ripple_fv_partition", "ripple_fv_halo_exchange", "ripple_fv_conserved_sums",
     "ripple_fv_error_norms", "ripple_fv_check", "ripple_fv_profile", "ripple_fv_status_string",
     "ripple_fv_last_error",
+    "ripple_force2d_grid_init", "ripple_force2d_import", "ripple_force2d_export",
+    "ripple_force2d_flux_difference",
 ]
+
+PADDED = 2             # ripple_force2d boundary kind: padding read as stored
+WITH_PADDING = 2       # ripple_force2d_import flag: source covers the padding ring
+NVAR2D = 4
 
 
 class Grid(ctypes.Structure):
@@ -68,6 +75,29 @@ class Grid(ctypes.Structure):
                 f"bytes={self.bytes})")
 
 
+class Force2DGrid(ctypes.Structure):
+    """ripple_force2d_grid."""
+    _fields_ = [
+        ("n", ctypes.c_int32 * 2),
+        ("bc", ctypes.c_int32 * 2),
+        ("layout", ctypes.c_int32),
+        ("dtype", ctypes.c_int32),
+        ("aosoa_w", ctypes.c_int32),
+        ("block", ctypes.c_int32),
+        ("segment", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("x_origin", ctypes.c_int32),
+        ("pad_", ctypes.c_int32),
+        ("pitch", ctypes.c_int64 * 2),
+        ("bytes", ctypes.c_int64),
+    ]
+
+    def __repr__(self):
+        return (f"Force2DGrid(n={list(self.n)}, bc={list(self.bc)}, layout={self.layout}, "
+                f"dtype={self.dtype}, aosoa_w={self.aosoa_w}, block={self.block}, "
+                f"segment={self.segment}, bytes={self.bytes})")
+
+
 class RippleFVError(RuntimeError):
     def __init__(self, status, message):
         self.status = status
@@ -94,6 +124,7 @@ def _declare(L):
     st = ctypes.c_int32
     vp = ctypes.c_void_p
     gp = ctypes.POINTER(Grid)
+    fp = ctypes.POINTER(Force2DGrid)
     dp = ctypes.POINTER(ctypes.c_double)
     sig = {
         "ripple_fv_grid_init": (st, [gp]),
@@ -119,6 +150,11 @@ def _declare(L):
         "ripple_fv_profile": (st, [vp, dp, ctypes.POINTER(ctypes.c_int64)]),
         "ripple_fv_status_string": (ctypes.c_char_p, [st]),
         "ripple_fv_last_error": (ctypes.c_char_p, [vp]),
+        "ripple_force2d_grid_init": (st, [fp]),
+        "ripple_force2d_import": (st, [vp, fp, vp, ctypes.c_int32, vp, vp]),
+        "ripple_force2d_export": (st, [vp, fp, vp, vp, vp]),
+        "ripple_force2d_flux_difference": (st, [vp, fp, vp, ctypes.c_double, ctypes.c_double,
+                                                vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -257,6 +293,24 @@ def ripple_fv_last_error(ctx):
     return lib().ripple_fv_last_error(ctx).decode()
 
 
+def ripple_force2d_grid_init(g):
+    _check(lib().ripple_force2d_grid_init(ctypes.byref(g)))
+    return g
+
+
+def ripple_force2d_import(ctx, g, src, variables, u, stream=None):
+    _check(lib().ripple_force2d_import(ctx, ctypes.byref(g), src, int(variables), u, stream), ctx)
+
+
+def ripple_force2d_export(ctx, g, u, dst, stream=None):
+    _check(lib().ripple_force2d_export(ctx, ctypes.byref(g), u, dst, stream), ctx)
+
+
+def ripple_force2d_flux_difference(ctx, g, u, lam_x, lam_y, d, stream=None):
+    _check(lib().ripple_force2d_flux_difference(ctx, ctypes.byref(g), u, float(lam_x),
+                                                float(lam_y), d, stream), ctx)
+
+
 def call(name, *args):
     """Raw call of a C entry point; returns its status without raising."""
     return getattr(lib(), name)(*args)
@@ -298,3 +352,18 @@ def copy_grid(g, **changes):
         else:
             setattr(h, k, v)
     return ripple_fv_grid_init(h)
+
+
+def make_force2d_grid(n, dtype=F64, layout=SOA, bc=(TRANSMISSIVE,) * 2, aosoa_w=0, block=0,
+                      segment=0):
+    """A ripple_force2d_grid with x_origin, pitch and bytes filled."""
+    g = Force2DGrid()
+    for d in range(2):
+        g.n[d] = int(n[d])
+        g.bc[d] = int(bc[d])
+    g.layout = int(layout)
+    g.dtype = int(dtype)
+    g.aosoa_w = int(aosoa_w)
+    g.block = int(block)
+    g.segment = int(segment)
+    return ripple_force2d_grid_init(g)

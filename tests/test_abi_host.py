@@ -13,10 +13,13 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def declared_functions():
-    with open(os.path.join(ROOT, "include", "ripple_fv.h")) as f:
-        text = f.read()
-    decl = r"^(?:ripple_fv_status|void|const char\*)\s+(ripple_fv_[a-z_]+)\("
-    return sorted(set(re.findall(decl, text, flags=re.M)))
+    names = set()
+    for header in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        with open(os.path.join(ROOT, "include", header)) as f:
+            text = f.read()
+        decl = r"^(?:ripple_fv_status|void|const char\*)\s+(ripple_(?:fv|force2d)_[a-z_]+)\("
+        names.update(re.findall(decl, text, flags=re.M))
+    return sorted(names)
 
 
 def test_header_and_binding_agree():
@@ -124,3 +127,70 @@ def test_partition_rejects_too_thin():
     whole = R.make_grid((6, 6, 6))
     with pytest.raises(R.RippleFVError):
         R.ripple_fv_partition(whole, (4, 1, 1))
+
+
+# -- two-dimensional flux-difference descriptors ----------------------------------
+
+def test_force2d_struct_size():
+    # 2*4 + 2*4 + 8*4 + 2*8 + 8, no padding holes
+    assert ctypes.sizeof(R.Force2DGrid) == 72
+    assert R.Force2DGrid.pitch.offset == 48
+
+
+def test_force2d_grid_init_pitches():
+    def slots2(px, py, ox):
+        return (px * py + ox + 63) // 64 * 64
+    g = R.make_force2d_grid((1000, 37), dtype=R.F32, layout=R.SOA)
+    assert list(g.pitch) == [1024, 39] and g.x_origin == 32
+    assert g.bytes == slots2(1024, 39, 32) * 4 * 4
+    g = R.make_force2d_grid((14, 3), dtype=R.F64, layout=R.SOA)
+    assert list(g.pitch) == [16, 5] and g.x_origin == 16
+    g = R.make_force2d_grid((15, 3), dtype=R.F64, layout=R.SOA)
+    assert list(g.pitch) == [32, 5]
+    g = R.make_force2d_grid((5, 3), dtype=R.F64, layout=R.AOS)
+    assert list(g.pitch) == [7, 5] and g.x_origin == 1
+    assert g.bytes == slots2(7, 5, 1) * 4 * 8
+    g = R.make_force2d_grid((5, 3), dtype=R.F32, layout=R.AOSOA, aosoa_w=64)
+    assert list(g.pitch) == [64, 5] and g.x_origin == 64
+    g = R.make_force2d_grid((1, 1), dtype=R.F32, layout=R.AOSOA, aosoa_w=16)
+    assert list(g.pitch) == [32, 3] and g.x_origin == 32
+
+
+def test_force2d_rows_do_not_overlap():
+    """Every cell of [-1, n]^2 has its own slot inside the buffer, and SoA /
+    AoSoA interior rows start on 128-byte lines."""
+    import numpy as np
+    for layout, w in ((R.AOS, 0), (R.SOA, 0), (R.AOSOA, 16), (R.AOSOA, 64)):
+        for dt in (R.F32, R.F64):
+            for n in ((13, 5), (1, 1), (64, 2)):
+                g = R.make_force2d_grid(n, dtype=dt, layout=layout, aosoa_w=w)
+                s = 4 if dt == R.F32 else 8
+                i = np.arange(-1, n[0] + 1)[None, :]
+                j = np.arange(-1, n[1] + 1)[:, None]
+                q = (j + 1) * g.pitch[0] + i + g.x_origin
+                assert len(np.unique(q)) == q.size
+                assert q.min() >= 0 and q.max() < g.bytes // (4 * s)
+                if layout != R.AOS:
+                    assert all(((jj + 1) * g.pitch[0] + g.x_origin) * s % 128 == 0
+                               for jj in range(n[1]))
+
+
+@pytest.mark.parametrize("bad", [
+    dict(n=(0, 4)), dict(n=(4, 0)), dict(n=((1 << 20) + 1, 4)), dict(dtype=2), dict(layout=3),
+    dict(layout=R.AOSOA, aosoa_w=8), dict(layout=R.SOA, aosoa_w=16), dict(bc=(0, 3)),
+    dict(bc=(-1, 0)), dict(block=32), dict(block=2048), dict(segment=-1),
+])
+def test_force2d_grid_init_rejects(bad):
+    kw = dict(n=(8, 8))
+    kw.update(bad)
+    with pytest.raises(R.RippleFVError) as e:
+        R.make_force2d_grid(**kw)
+    assert e.value.status == R.E_INVALID
+
+
+def test_force2d_reserved_must_be_zero():
+    g = R.Force2DGrid()
+    g.n[0] = g.n[1] = 8
+    g.layout = R.SOA
+    g.reserved = 1
+    assert R.call("ripple_force2d_grid_init", ctypes.byref(g)) == R.E_INVALID

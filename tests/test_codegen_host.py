@@ -1,5 +1,5 @@
 """Properties of the compiled gfx950 kernels, checked on the host from the
-assembly hipcc emits for the kernel translation unit (no GPU needed):
+assembly hipcc emits for the kernel translation units (no GPU needed):
 no kernel spills into accumulation registers or scratch memory, and none
 uses packed FP32 arithmetic."""
 import os
@@ -14,15 +14,15 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, os.path.join(ROOT, "paper_2104_08571_amd"))
 
 
-@pytest.fixture(scope="module")
-def assembly(tmp_path_factory):
+@pytest.fixture(scope="module", params=["fv_kernels.hip", "force2d.hip"])
+def assembly(request, tmp_path_factory):
     import build
     hipcc = build._hipcc()
     if not (os.path.exists(hipcc) or shutil.which(hipcc)):
         pytest.skip("needs hipcc")
-    out = str(tmp_path_factory.mktemp("asm") / "fv_kernels.s")
+    out = str(tmp_path_factory.mktemp("asm") / (request.param + ".s"))
     cmd = [hipcc, *build.HIPCC_FLAGS, "--cuda-device-only", "-S",
-           os.path.join(build.CSRC, "fv_kernels.hip"), "-o", out]
+           os.path.join(build.CSRC, request.param), "-o", out]
     subprocess.run(cmd, check=True, capture_output=True)
     with open(out) as f:
         return f.read()
