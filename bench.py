@@ -12,7 +12,9 @@ duration, timed with HIP events around every launch inside the timed region;
 `cpu_baseline` times the FP64 CPU oracle on a bounded sample of the same
 workload on this host.  `force2d_flux_difference` reports the 2D FORCE
 flux-difference benchmark (square grids of 1024^2 .. 32768^2 cells, FP32 and
-FP64, strided and contiguous layouts), one computation per call.
+FP64, strided and contiguous layouts), one computation per call;
+`shock_bubble_2d` the 2D split Euler solver on the shock-bubble problem at
+6400 x 4000 and 9600 x 6000 cells, 1000 steps.
 """
 import argparse
 import hashlib
@@ -195,6 +197,67 @@ def run_partition_workload(steps, warmup):
     return out
 
 
+def run_shock_bubble_workload(sizes, dtypes, steps, warmup):
+    """The paper's 2D scaling application on one GPU: the split Euler solver
+    (wave speeds -> dt -> x sweep -> y sweep per step) on a Mach 3.81 shock
+    hitting a low-density bubble, transmissive faces, `steps` steps replayed
+    from hipGraphs, state resident in HBM; per-sweep times from a separate
+    profiled run of a few steps."""
+    import torch
+
+    from paper_2104_08571_amd import initial_states as ist
+    from paper_2104_08571_amd import ripple_fv as R
+
+    ctx = R.ripple_fv_create(0)
+    stream = torch.cuda.current_stream().cuda_stream
+    rows = []
+    try:
+        for dt_name in dtypes:
+            dtype = R.F32 if dt_name == "f32" else R.F64
+            for nx, ny in sizes:
+                g = R.make_grid((nx, ny, 1), dtype=dtype, layout=R.SOA, bc=(0, 0, 0),
+                                dx=(1.0 / ny, 1.0 / ny, 1.0))
+                W = ist.shock_bubble(nx, ny, device="cuda")
+                a = torch.empty(g.bytes, dtype=torch.uint8, device="cuda")
+                b = torch.empty(g.bytes, dtype=torch.uint8, device="cuda")
+                pa, pb = [a.data_ptr()], [b.data_ptr()]
+
+                def load():
+                    R.ripple_fv_import(ctx, g, W.data_ptr(), R.PRIMITIVE, a.data_ptr(), stream)
+
+                load()
+                R.ripple_fv_run_batch(ctx, [g], pa, pb, warmup, 0.9, R.RUN_EAGER, stream)
+                R.ripple_fv_profile(ctx)
+                R.ripple_fv_run_batch(ctx, [g], pa, pb, 5, 0.9, R.RUN_PROFILE, stream)
+                torch.cuda.synchronize()
+                prof = R.ripple_fv_profile(ctx)
+                # capture the graphs of this step count before timing
+                load()
+                R.ripple_fv_run_batch(ctx, [g], pa, pb, steps, 0.9, R.RUN_GRAPH, stream)
+                load()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                R.ripple_fv_run_batch(ctx, [g], pa, pb, steps, 0.9, R.RUN_GRAPH, stream)
+                torch.cuda.synchronize()
+                secs = time.perf_counter() - t0
+                t_end, _ = R.ripple_fv_batch_time(ctx, [g])
+                cells = nx * ny
+                row = {"nx": nx, "ny": ny, "dtype": dt_name, "steps": steps,
+                       "seconds": round(secs, 4), "ms_per_step": round(secs / steps * 1e3, 4),
+                       "gcell_updates_per_s": round(cells * steps / secs / 1e9, 3),
+                       "t_reached": t_end[0],
+                       "kernel_ms": {k: round(ms / c, 4) for k, (ms, c) in prof.items() if c},
+                       "status": R.ripple_fv_check(ctx)}
+                rows.append(row)
+                print(f"[bench] shock bubble {dt_name} {nx}x{ny}: {row}", file=sys.stderr,
+                      flush=True)
+                del W, a, b
+                torch.cuda.empty_cache()
+    finally:
+        R.ripple_fv_destroy(ctx)
+    return {"workload": "shock_bubble_2d_mach3.81", "results": rows}
+
+
 # The paper's table of the 2D flux difference ("tab:flux", one V100, ms per
 # computation) for the strided and contiguous layouts -- other hardware,
 # reported as context only.
@@ -368,6 +431,11 @@ def main():
     ap.add_argument("--force2d-sizes", default="1024,2048,4096,8192,16384,32768")
     ap.add_argument("--force2d-layouts", default="soa,aos")
     ap.add_argument("--force2d-dtypes", default="f32,f64")
+    ap.add_argument("--no-shock-bubble", action="store_true",
+                    help="skip the 2D shock-bubble solver leg")
+    ap.add_argument("--shock-bubble-only", action="store_true",
+                    help="run only the 2D shock-bubble solver leg (prints its JSON)")
+    ap.add_argument("--shock-bubble-steps", type=int, default=1000)
     ap.add_argument("--copy-only", action="store_true",
                     help="only run the plain-copy calibration (2 GiB, 20 copies) and print it")
     args = ap.parse_args()
@@ -381,6 +449,10 @@ def main():
         return
     f2_args = ([int(v) for v in args.force2d_sizes.split(",")], args.force2d_dtypes.split(","),
                args.force2d_layouts.split(","), max(args.steps, 5), args.warmup)
+    sb_args = ([(6400, 4000), (9600, 6000)], ["f32", "f64"], args.shock_bubble_steps, args.warmup)
+    if args.shock_bubble_only:
+        print(json.dumps({"shock_bubble_2d": run_shock_bubble_workload(*sb_args)}), flush=True)
+        return
     if args.force2d_only:
         print(json.dumps({"force2d_flux_difference": run_force2d_workload(*f2_args)}), flush=True)
         return
@@ -437,6 +509,9 @@ def main():
         part = run_partition_workload(args.steps, args.warmup)
         print(f"[bench] partition 768^3: {part}", file=sys.stderr, flush=True)
 
+    sb = None
+    if not args.no_shock_bubble:
+        sb = run_shock_bubble_workload(*sb_args)
     f2 = None
     if not args.no_force2d:
         f2 = run_force2d_workload(*f2_args)
@@ -483,6 +558,8 @@ def main():
         out["batch_64_grids_f32"] = batch
     if part is not None:
         out["partition_768_f32_2x2x2"] = part
+    if sb is not None:
+        out["shock_bubble_2d"] = sb
     if f2 is not None:
         out["force2d_flux_difference"] = f2
     print(json.dumps(out), flush=True)

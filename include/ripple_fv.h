@@ -93,7 +93,12 @@ enum ripple_fv_kernel_kind {
 
 /* Grid descriptor.  Fill the inputs, then call ripple_fv_grid_init.
  *
- *  n        interior extents (x, y, z), each >= 2
+ *  n        interior extents (x, y, z), each >= 1.  An axis one cell thick
+ *           makes the grid planar along it: a sweep along that axis reads
+ *           the same state on both faces of every cell and changes nothing,
+ *           and its periodic and transmissive faces coincide (a two-
+ *           dimensional problem is a grid with n[2] = 1 and a dx[2] large
+ *           enough that dx[2] / S_z never sets the time step)
  *  bc       boundary condition per axis, applied on both faces that are
  *           physical boundaries (transmissive = constant extrapolation of the
  *           edge cell into the padding; periodic = wrap)
@@ -165,7 +170,7 @@ typedef struct ripple_fv_ctx ripple_fv_ctx;
  * 128 bytes / element size (32 for F32, 16 for F64).  AOSOA: the same with
  * A = max(128 bytes / element size, aosoa_w).  The cell-slot count
  * C = Px Py Pz + x_origin rounded up to a multiple of 64.
- * E_INVALID on extents < 2, dx <= 0, unknown enums, bad aosoa_w, bad tiling
+ * E_INVALID on extents < 1, dx <= 0, unknown enums, bad aosoa_w, bad tiling
  * knobs, or a buffer size above 2^46 bytes. */
 ripple_fv_status ripple_fv_grid_init(ripple_fv_grid* g);
 
@@ -219,7 +224,8 @@ ripple_fv_status ripple_fv_sweep(ripple_fv_ctx* ctx, const ripple_fv_grid* g, in
  * state before and after; work is a second buffer of g->bytes that the step
  * clobbers (where the x and y sweeps run as one fused pass the step is
  * u -> work -> u; otherwise the three sweeps ping-pong and the result is
- * copied back).  cfl in (0, 1].  dt_dev: optional device double receiving
+ * copied back; one cell thick in z: u -> work -> u by the x and y sweeps
+ * alone).  cfl in (0, 1].  dt_dev: optional device double receiving
  * the dt used. */
 ripple_fv_status ripple_fv_step(ripple_fv_ctx* ctx, const ripple_fv_grid* g, void* u,
                                 void* work, double cfl, double dt, double* dt_dev,
@@ -238,7 +244,10 @@ ripple_fv_status ripple_fv_step(ripple_fv_ctx* ctx, const ripple_fv_grid* g, voi
  * All grids must share layout, dtype and tiling knobs (else E_UNSUPPORTED).
  * flags: ripple_fv_run_flags.  The first call for a given set of grid
  * descriptors builds and caches a plan (workspaces, tile lists, graphs);
- * later calls with the same descriptors allocate nothing. */
+ * later calls with the same descriptors allocate nothing.  When every grid
+ * is one cell thick in z and the x and y sweeps run separately, a step is
+ * x (u -> work) and y (work -> u) only: the z sweep would change nothing,
+ * and the y sweep reduces the next step's wave speeds instead. */
 ripple_fv_status ripple_fv_run_batch(ripple_fv_ctx* ctx, int32_t n, const ripple_fv_grid* grids,
                                      void* const* u, void* const* work, int32_t nsteps,
                                      double cfl, int32_t flags, void* stream);
@@ -263,7 +272,8 @@ ripple_fv_status ripple_fv_batch_tune(ripple_fv_ctx* ctx, int32_t n, const rippl
  * of parts descriptors, x fastest, each with its own extents (extents split
  * as evenly as possible), dx, nbr links (batch indices offset by
  * first_index) and group = first_index.  The whole grid's periodic axes are
- * linked around. */
+ * linked around, except one-cell axes.  A split axis keeps at least 2 cells
+ * per sub-block. */
 ripple_fv_status ripple_fv_partition(const ripple_fv_grid* whole, const int32_t parts[3],
                                      int32_t first_index, ripple_fv_grid* sub);
 

@@ -32,6 +32,10 @@ struct Plan {
   Tiling tl{};
   std::vector<ripple_fv_grid> grids;
   bool fused = false;                   // x and y sweeps as one pass
+  bool planar = false;                  // separate sweeps, every grid one cell thick in z
+  // the step returns the state to its first buffer (else the separate sweeps
+  // alternate the two buffers from step to step)
+  bool in_place() const { return fused || planar; }
   std::vector<int64_t> tiles[5];        // prefix: x, y, z, wave-speed, fused x-y tiles
   std::vector<HaloTask> halo[3];
   int64_t halo_area[3] = {0, 0, 0};
@@ -125,7 +129,7 @@ bool valid_block(int v, std::initializer_list<int> allowed) {
 ripple_fv_status grid_check(const ripple_fv_grid* g, int64_t pitch[3], int64_t* bytes,
                             int32_t* x_origin, std::string* why) {
   for (int d = 0; d < 3; ++d) {
-    if (g->n[d] < 2) { *why = "extent < 2"; return RIPPLE_FV_E_INVALID; }
+    if (g->n[d] < 1) { *why = "extent < 1"; return RIPPLE_FV_E_INVALID; }
     if (!(g->dx[d] > 0.0) || !std::isfinite(g->dx[d])) { *why = "dx <= 0"; return RIPPLE_FV_E_INVALID; }
     if (g->bc[d] != RIPPLE_FV_TRANSMISSIVE && g->bc[d] != RIPPLE_FV_PERIODIC) {
       *why = "unknown boundary condition";
@@ -311,6 +315,8 @@ ripple_fv_status build_plan(ripple_fv_ctx* ctx, int n, const ripple_fv_grid* gri
   P->grids.assign(grids, grids + n);
   P->fused = !P->tl.split_xy;
   for (int g = 0; g < n; ++g) P->fused = P->fused && xy_eligible(grids[g]);
+  P->planar = !P->fused;
+  for (int g = 0; g < n; ++g) P->planar = P->planar && grids[g].n[2] == 1;
   for (int k = 0; k < 5; ++k) P->tiles[k].assign(n + 1, 0);
   for (int g = 0; g < n; ++g) {
     P->tiles[4][g + 1] = P->tiles[4][g] + (P->fused ? tiles_xy(grids[g], P->tl.yz_segment) : 0);
@@ -349,8 +355,11 @@ ripple_fv_status build_plan(ripple_fv_ctx* ctx, int n, const ripple_fv_grid* gri
       D.dx[d] = G.dx[d];
       for (int side = 0; side < 2; ++side) {
         const int f = 2 * d + side;
+        // a one-cell axis is its own periodic image: transmissive and periodic
+        // faces then read the same cell
         D.mode[f] = G.nbr[f] >= 0 ? FACE_HALO
-                                  : (G.bc[d] == RIPPLE_FV_PERIODIC ? FACE_PERIODIC : FACE_TRANSMISSIVE);
+                    : (G.bc[d] == RIPPLE_FV_PERIODIC && G.n[d] >= 2 ? FACE_PERIODIC
+                                                                     : FACE_TRANSMISSIVE);
       }
     }
     D.px = G.pitch[0];
@@ -609,6 +618,13 @@ ripple_fv_status enqueue_step(ripple_fv_ctx* ctx, Plan* P, Launcher& L, int cur,
   if (!st) st = enqueue_halo(ctx, P, L, 0, cur);
   if (!st) st = enqueue_sweep(ctx, P, L, 0, cur, oth, 0, per_grid);
   if (!st) st = enqueue_halo(ctx, P, L, 1, oth);
+  if (P->planar) {
+    // a sweep along a one-cell axis reads the same state on both faces of
+    // every cell and leaves it unchanged bit for bit: skip it, and let the y
+    // sweep reduce the wave speeds for the next step instead
+    if (!st) st = enqueue_sweep(ctx, P, L, 1, oth, cur, 1, per_grid);
+    return st;
+  }
   if (!st) st = enqueue_sweep(ctx, P, L, 1, oth, cur, 0, per_grid);
   if (!st) st = enqueue_halo(ctx, P, L, 2, cur);
   if (!st) st = enqueue_sweep(ctx, P, L, 2, cur, oth, 1, per_grid);
@@ -631,7 +647,7 @@ ripple_fv_status capture_graph(ripple_fv_ctx* ctx, Plan* P, int nsteps, double c
   Launcher L{ctx, cs, false, {}, 0};
   ripple_fv_status st = RIPPLE_FV_OK;
   for (int k = 0; k < nsteps && !st; ++k)
-    st = enqueue_step(ctx, P, L, P->fused ? 0 : (k & 1), cfl, 0.0, nullptr, per_grid);
+    st = enqueue_step(ctx, P, L, P->in_place() ? 0 : (k & 1), cfl, 0.0, nullptr, per_grid);
   hipGraph_t graph = nullptr;
   hipError_t e = hipStreamEndCapture(cs, &graph);
   if (st) {
@@ -696,7 +712,7 @@ ripple_fv_status run(ripple_fv_ctx* ctx, int n, const ripple_fv_grid* grids, voi
     // even count on the separate-sweep path, whose steps alternate buffers),
     // then one graph for the remainder; graphs are cached by step count
     int chunk = std::min(nsteps, GRAPH_MAX_STEPS);
-    if (!P->fused && chunk > 1) chunk &= ~1;
+    if (!P->in_place() && chunk > 1) chunk &= ~1;
     auto graph_for = [&](int k, hipGraphExec_t* out) -> ripple_fv_status {
       auto it = P->graphs.find(k);
       if (it != P->graphs.end()) {
@@ -716,14 +732,14 @@ ripple_fv_status run(ripple_fv_ctx* ctx, int n, const ripple_fv_grid* grids, voi
     for (int k = 0; k + chunk <= nsteps; k += chunk) HIP_OR_FAIL(ctx, hipGraphLaunch(gc, s));
     if (rem) HIP_OR_FAIL(ctx, hipGraphLaunch(gr, s));
     // (the copy back stays outside the graphs: its pointers change with the buffers)
-    if (!P->fused && (nsteps & 1)) return enqueue_copy_back(ctx, P, s);
+    if (!P->in_place() && (nsteps & 1)) return enqueue_copy_back(ctx, P, s);
     return RIPPLE_FV_OK;
   }
   for (int k = 0; k < nsteps; ++k) {
-    if ((st = enqueue_step(ctx, P, L, P->fused ? 0 : (k & 1), cfl, fixed_dt, dt_out, per_grid)))
+    if ((st = enqueue_step(ctx, P, L, P->in_place() ? 0 : (k & 1), cfl, fixed_dt, dt_out, per_grid)))
       return st;
   }
-  if (!P->fused && (nsteps & 1) && (st = enqueue_copy_back(ctx, P, s))) return st;
+  if (!P->in_place() && (nsteps & 1) && (st = enqueue_copy_back(ctx, P, s))) return st;
   return L.collect();
 }
 
@@ -944,7 +960,7 @@ ripple_fv_status ripple_fv_partition(const ripple_fv_grid* whole, const int32_t 
   std::string why;
   if (grid_check(whole, pitch, &bytes, &ox, &why)) return RIPPLE_FV_E_INVALID;
   for (int d = 0; d < 3; ++d)
-    if (parts[d] < 1 || whole->n[d] / parts[d] < 2) return RIPPLE_FV_E_INVALID;
+    if (parts[d] < 1 || (parts[d] > 1 && whole->n[d] / parts[d] < 2)) return RIPPLE_FV_E_INVALID;
   for (int d = 0; d < 3; ++d)
     if (whole->nbr[d * 2] >= 0 || whole->nbr[d * 2 + 1] >= 0) return RIPPLE_FV_E_INVALID;
   const int px = parts[0], py = parts[1], pz = parts[2];
@@ -964,8 +980,10 @@ ripple_fv_status ripple_fv_partition(const ripple_fv_grid* whole, const int32_t 
             nb[d] += side == 0 ? -1 : 1;
             const bool inside = nb[d] >= 0 && nb[d] < np;
             if (!inside && whole->bc[d] == RIPPLE_FV_PERIODIC) nb[d] = (nb[d] + np) % np;
+            // (a one-cell axis is not linked to itself: its faces read the cell)
             S.nbr[2 * d + side] =
-                (inside || whole->bc[d] == RIPPLE_FV_PERIODIC) ? idx(nb[0], nb[1], nb[2]) : -1;
+                (inside || (whole->bc[d] == RIPPLE_FV_PERIODIC && nn >= 2)) ? idx(nb[0], nb[1], nb[2])
+                                                                           : -1;
           }
         }
         S.group = first_index;

@@ -930,7 +930,9 @@ static hipError_t sweep_yz_cols(int axis, const Tiling& tl, const SweepParams& p
   const DevGrid* G = p.w.grids;
   const int64_t* TS = p.tiles.tile_start;
   const double* L = p.w.lam;
-  if (axis == 1)
+  if (axis == 1 && p.fuse_s)   // last sweep of a step on grids one cell thick in z
+    hipLaunchKernelGGL((k_sweep_yz<T, LAY, 1, true, COLS>), dim3(blocks), dim3(tl.yz_block), 0, s, p, G, TS, L);
+  else if (axis == 1)
     hipLaunchKernelGGL((k_sweep_yz<T, LAY, 1, false, COLS>), dim3(blocks), dim3(tl.yz_block), 0, s, p, G, TS, L);
   else if (p.fuse_s)
     hipLaunchKernelGGL((k_sweep_yz<T, LAY, 2, true, COLS>), dim3(blocks), dim3(tl.yz_block), 0, s, p, G, TS, L);

@@ -151,6 +151,34 @@ def blast(n, origin=None, n_global=None, device="cpu", radius=0.1,
     return W
 
 
+def shock_bubble(nx, ny, device="cpu", mach=3.81, x_shock=0.1, centre=(0.4, 0.5),
+                 radius=0.2, rho_bubble=0.1, gamma=1.4):
+    """Planar shock-bubble interaction on an nx x ny x 1 grid of square cells
+    over [0, nx/ny] x [0, 1]: ambient gas at rest (rho = 1, p = 1); a shock of
+    Mach number `mach` at x = x_shock moving towards +x, the gas behind it
+    (x_c < x_shock) in the post-shock state of the normal-shock relations,
+        rho2 = (g + 1) M^2 / ((g - 1) M^2 + 2),
+        p2 = (2 g M^2 - (g - 1)) / (g + 1),
+        u2 = M c1 (1 - 1 / rho2),  c1 = sqrt(g);
+    and a bubble of density rho_bubble at ambient pressure, at rest, where
+    the cell centre lies strictly within `radius` of `centre`."""
+    h = 1.0 / ny
+    x = (torch.arange(nx, dtype=torch.float64, device=device) + 0.5) * h
+    y = (torch.arange(ny, dtype=torch.float64, device=device) + 0.5) * h
+    m2 = mach * mach
+    rho2 = (gamma + 1.0) * m2 / ((gamma - 1.0) * m2 + 2.0)
+    p2 = (2.0 * gamma * m2 - (gamma - 1.0)) / (gamma + 1.0)
+    u2 = mach * math.sqrt(gamma) * (1.0 - 1.0 / rho2)
+    behind = (x < x_shock)[None, :].expand(ny, nx)
+    inside = ((x - centre[0]) ** 2)[None, :] + ((y - centre[1]) ** 2)[:, None] < radius * radius
+    W = torch.zeros((5, 1, ny, nx), dtype=torch.float64, device=device)
+    W[0, 0] = torch.where(behind, _f64(rho2, device),
+                          torch.where(inside, _f64(rho_bubble, device), _f64(1.0, device)))
+    W[1, 0] = torch.where(behind, _f64(u2, device), _f64(0.0, device))
+    W[4, 0] = torch.where(behind, _f64(p2, device), _f64(1.0, device))
+    return W
+
+
 def uniform(n, rho=1.0, u=0.0, v=0.0, w=0.0, p=1.0, device="cpu"):
     """Constant state."""
     n = tuple(int(v_) for v_ in n)

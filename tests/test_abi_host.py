@@ -79,7 +79,7 @@ def test_grid_rows_do_not_overlap():
 
 
 @pytest.mark.parametrize("bad", [
-    dict(n=(1, 4, 4)), dict(n=(4, 4, 0)), dict(dx=(0.0, 0.1, 0.1)), dict(dx=(-1.0, 0.1, 0.1)),
+    dict(n=(0, 4, 4)), dict(n=(4, 4, 0)), dict(n=(4, -1, 4)), dict(dx=(0.0, 0.1, 0.1)), dict(dx=(-1.0, 0.1, 0.1)),
     dict(dtype=2), dict(layout=3), dict(layout=R.AOSOA, aosoa_w=8), dict(layout=R.SOA, aosoa_w=16),
     dict(bc=(0, 2, 0)), dict(tiling=(64, 0, 0, 0)), dict(tiling=(0, 512, 0, 0)),
     dict(tiling=(0, 0, 2, 0)), dict(tiling=(0, 0, 0, -1)), dict(tiling=(0, 0, 0, 0, 3)),
@@ -127,6 +127,19 @@ def test_partition_rejects_too_thin():
     whole = R.make_grid((6, 6, 6))
     with pytest.raises(R.RippleFVError):
         R.ripple_fv_partition(whole, (4, 1, 1))
+
+
+def test_planar_grids_and_partition():
+    """One-cell axes are accepted; a periodic one-cell axis is not linked to
+    itself by the partition, and a split axis keeps two cells per block."""
+    g = R.make_grid((64, 40, 1), bc=(1, 1, 1))
+    assert list(g.pitch) == [g.pitch[0], 44, 5]
+    subs = R.ripple_fv_partition(g, (2, 1, 1))
+    assert [list(s.nbr) for s in subs] == [[1, 1, 0, 0, -1, -1], [0, 0, 1, 1, -1, -1]]
+    assert all(s.n[2] == 1 for s in subs)
+    with pytest.raises(R.RippleFVError):
+        R.ripple_fv_partition(g, (1, 1, 2))
+    R.make_grid((1, 1, 1))
 
 
 # -- two-dimensional flux-difference descriptors ----------------------------------
