@@ -14,7 +14,9 @@ workload on this host.  `force2d_flux_difference` reports the 2D FORCE
 flux-difference benchmark (square grids of 1024^2 .. 32768^2 cells, FP32 and
 FP64, strided and contiguous layouts), one computation per call;
 `shock_bubble_2d` the 2D split Euler solver on the shock-bubble problem at
-6400 x 4000 and 9600 x 6000 cells, 1000 steps.
+6400 x 4000 and 9600 x 6000 cells, 1000 steps; `particle_update` the 3D
+particle update x += v dt (100 thousand to 80 million particles, FP32 and
+FP64, strided, contiguous and blocked layouts).
 """
 import argparse
 import hashlib
@@ -258,6 +260,76 @@ def run_shock_bubble_workload(sizes, dtypes, steps, warmup):
     return {"workload": "shock_bubble_2d_mach3.81", "results": rows}
 
 
+# The paper's particle-update table ("tab:particle_update", one V100, ms per
+# update) for the strided and contiguous layouts -- context only.
+PAPER_PARTICLE_MS = {"soa": {100_000: 0.0191, 1_000_000: 0.1036, 10_000_000: 0.8679,
+                             20_000_000: 1.7146, 40_000_000: 3.4062, 80_000_000: 6.7914},
+                     "aos": {100_000: 0.0259, 1_000_000: 0.1620, 10_000_000: 1.4472,
+                             20_000_000: 2.8487, 40_000_000: 5.7184, 80_000_000: 11.452}}
+
+
+def run_particle_workload(sizes, dtypes, layouts, reps, warmup):
+    """Particle update x += v dt in place: mean and minimum time per update
+    from HIP events around every call on the launching stream; 9 elements
+    move per particle (6 read, 3 written)."""
+    import torch
+
+    from paper_2104_08571_amd import ripple_fv as R
+
+    ctx = R.ripple_fv_create(0)
+    stream = torch.cuda.current_stream()
+    lays = {"soa": (R.SOA, 0), "aos": (R.AOS, 0), "aosoa64": (R.AOSOA, 64)}
+    rows = []
+    try:
+        for dt_name in dtypes:
+            dtype = R.F32 if dt_name == "f32" else R.F64
+            s_bytes = 4 if dtype == R.F32 else 8
+            for lay_name in layouts:
+                for n in sizes:
+                    p = R.make_particles(n, dtype=dtype, layout=lays[lay_name][0],
+                                         aosoa_w=lays[lay_name][1])
+                    buf = torch.empty(p.bytes, dtype=torch.uint8, device="cuda")
+                    gen = torch.Generator(device="cuda").manual_seed(n)
+                    src = torch.rand((6, n), dtype=torch.float64, device="cuda", generator=gen)
+                    R.ripple_particles_import(ctx, p, src.data_ptr(), buf.data_ptr(),
+                                              stream.cuda_stream)
+                    del src
+                    for _ in range(warmup):
+                        R.ripple_particles_update(ctx, p, buf.data_ptr(), 1e-3, stream.cuda_stream)
+                    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+                    torch.cuda.synchronize()
+                    ev[0].record(stream)
+                    for k in range(reps):
+                        R.ripple_particles_update(ctx, p, buf.data_ptr(), 1e-3, stream.cuda_stream)
+                        ev[k + 1].record(stream)
+                    torch.cuda.synchronize()
+                    ms = [ev[k].elapsed_time(ev[k + 1]) for k in range(reps)]
+                    mean = sum(ms) / reps
+                    row = {"n": n, "dtype": dt_name, "layout": lay_name, "ms": round(mean, 4),
+                           "ms_min": round(min(ms), 4),
+                           "GBps_algorithmic": round(9 * s_bytes * n / mean / 1e6, 1)}
+                    if lay_name in PAPER_PARTICLE_MS and n in PAPER_PARTICLE_MS[lay_name]:
+                        row["paper_v100_ms"] = PAPER_PARTICLE_MS[lay_name][n]
+                    rows.append(row)
+                    print(f"[bench] particles {dt_name} {lay_name} {n}: {row}", file=sys.stderr,
+                          flush=True)
+                    del buf
+                    torch.cuda.empty_cache()
+    finally:
+        R.ripple_fv_destroy(ctx)
+    out = {"workload": "particle_update_3d", "reps": reps, "results": rows}
+    for r in rows:
+        if r["layout"] == "soa" and r["n"] == max(sizes):
+            key = f"particle_update_{r['n']}_{r['dtype']}_soa"
+            out[f"roofline_{r['dtype']}"] = {
+                "bound": "hbm", "kernel": "particles", "workload": key,
+                "achieved": r["GBps_algorithmic"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(r["GBps_algorithmic"] / PEAK_HBM_GBS, 4),
+                "traffic": measured_traffic("particles", key), "mean_launch_ms": r["ms"],
+                "bytes_per_launch_algorithmic": 9 * (4 if r["dtype"] == "f32" else 8) * r["n"]}
+    return out
+
+
 # The paper's table of the 2D flux difference ("tab:flux", one V100, ms per
 # computation) for the strided and contiguous layouts -- other hardware,
 # reported as context only.
@@ -436,6 +508,9 @@ def main():
     ap.add_argument("--shock-bubble-only", action="store_true",
                     help="run only the 2D shock-bubble solver leg (prints its JSON)")
     ap.add_argument("--shock-bubble-steps", type=int, default=1000)
+    ap.add_argument("--no-particles", action="store_true", help="skip the particle-update leg")
+    ap.add_argument("--particles-only", action="store_true",
+                    help="run only the particle-update leg (prints its JSON)")
     ap.add_argument("--copy-only", action="store_true",
                     help="only run the plain-copy calibration (2 GiB, 20 copies) and print it")
     args = ap.parse_args()
@@ -450,6 +525,11 @@ def main():
     f2_args = ([int(v) for v in args.force2d_sizes.split(",")], args.force2d_dtypes.split(","),
                args.force2d_layouts.split(","), max(args.steps, 5), args.warmup)
     sb_args = ([(6400, 4000), (9600, 6000)], ["f32", "f64"], args.shock_bubble_steps, args.warmup)
+    pt_args = ([100_000, 1_000_000, 10_000_000, 20_000_000, 40_000_000, 80_000_000],
+               ["f32", "f64"], ["soa", "aos", "aosoa64"], max(args.steps, 5), args.warmup)
+    if args.particles_only:
+        print(json.dumps({"particle_update": run_particle_workload(*pt_args)}), flush=True)
+        return
     if args.shock_bubble_only:
         print(json.dumps({"shock_bubble_2d": run_shock_bubble_workload(*sb_args)}), flush=True)
         return
@@ -512,6 +592,9 @@ def main():
     sb = None
     if not args.no_shock_bubble:
         sb = run_shock_bubble_workload(*sb_args)
+    pt = None
+    if not args.no_particles:
+        pt = run_particle_workload(*pt_args)
     f2 = None
     if not args.no_force2d:
         f2 = run_force2d_workload(*f2_args)
@@ -562,6 +645,8 @@ def main():
         out["shock_bubble_2d"] = sb
     if f2 is not None:
         out["force2d_flux_difference"] = f2
+    if pt is not None:
+        out["particle_update"] = pt
     print(json.dumps(out), flush=True)
 
 

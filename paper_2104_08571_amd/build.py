@@ -20,7 +20,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIBRARY = os.path.join(HERE, "libripple_fv.so")
 BUILD_DIR = os.path.join(HERE, "_build")
-SOURCES = ["fv_kernels.hip", "fv_api.hip", "force2d.hip"]
+SOURCES = ["fv_kernels.hip", "fv_api.hip", "force2d.hip", "particles.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-ffp-contract=off",

@@ -1,5 +1,5 @@
-"""ctypes binding of libripple_fv.so (declared in include/ripple_fv.h and
-include/ripple_force2d.h).
+"""ctypes binding of libripple_fv.so (declared in include/ripple_fv.h,
+include/ripple_force2d.h and include/ripple_particles.h).
 
 Argument marshalling only: every computation runs in the HIP library.  The
 functions keep the C names; each raises RippleFVError on a non-OK status
@@ -37,6 +37,8 @@ EXPORTED = [
     "ripple_fv_last_error",
     "ripple_force2d_grid_init", "ripple_force2d_import", "ripple_force2d_export",
     "ripple_force2d_flux_difference",
+    "ripple_particles_init", "ripple_particles_import", "ripple_particles_export",
+    "ripple_particles_update",
 ]
 
 PADDED = 2             # ripple_force2d boundary kind: padding read as stored
@@ -98,6 +100,21 @@ class Force2DGrid(ctypes.Structure):
                 f"segment={self.segment}, bytes={self.bytes})")
 
 
+class Particles(ctypes.Structure):
+    """ripple_particles."""
+    _fields_ = [
+        ("n", ctypes.c_int64),
+        ("layout", ctypes.c_int32),
+        ("dtype", ctypes.c_int32),
+        ("aosoa_w", ctypes.c_int32),
+        ("block", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("pad_", ctypes.c_int32),
+        ("slots", ctypes.c_int64),
+        ("bytes", ctypes.c_int64),
+    ]
+
+
 class RippleFVError(RuntimeError):
     def __init__(self, status, message):
         self.status = status
@@ -125,6 +142,7 @@ def _declare(L):
     vp = ctypes.c_void_p
     gp = ctypes.POINTER(Grid)
     fp = ctypes.POINTER(Force2DGrid)
+    pp = ctypes.POINTER(Particles)
     dp = ctypes.POINTER(ctypes.c_double)
     sig = {
         "ripple_fv_grid_init": (st, [gp]),
@@ -155,6 +173,10 @@ def _declare(L):
         "ripple_force2d_export": (st, [vp, fp, vp, vp, vp]),
         "ripple_force2d_flux_difference": (st, [vp, fp, vp, ctypes.c_double, ctypes.c_double,
                                                 vp, vp]),
+        "ripple_particles_init": (st, [pp]),
+        "ripple_particles_import": (st, [vp, pp, vp, vp, vp]),
+        "ripple_particles_export": (st, [vp, pp, vp, vp, vp]),
+        "ripple_particles_update": (st, [vp, pp, vp, ctypes.c_double, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -311,6 +333,23 @@ def ripple_force2d_flux_difference(ctx, g, u, lam_x, lam_y, d, stream=None):
                                                 float(lam_y), d, stream), ctx)
 
 
+def ripple_particles_init(p):
+    _check(lib().ripple_particles_init(ctypes.byref(p)))
+    return p
+
+
+def ripple_particles_import(ctx, p, src, buf, stream=None):
+    _check(lib().ripple_particles_import(ctx, ctypes.byref(p), src, buf, stream), ctx)
+
+
+def ripple_particles_export(ctx, p, buf, dst, stream=None):
+    _check(lib().ripple_particles_export(ctx, ctypes.byref(p), buf, dst, stream), ctx)
+
+
+def ripple_particles_update(ctx, p, buf, dt, stream=None):
+    _check(lib().ripple_particles_update(ctx, ctypes.byref(p), buf, float(dt), stream), ctx)
+
+
 def call(name, *args):
     """Raw call of a C entry point; returns its status without raising."""
     return getattr(lib(), name)(*args)
@@ -367,3 +406,14 @@ def make_force2d_grid(n, dtype=F64, layout=SOA, bc=(TRANSMISSIVE,) * 2, aosoa_w=
     g.block = int(block)
     g.segment = int(segment)
     return ripple_force2d_grid_init(g)
+
+
+def make_particles(n, dtype=F32, layout=SOA, aosoa_w=0, block=0):
+    """A ripple_particles descriptor with slots and bytes filled."""
+    p = Particles()
+    p.n = int(n)
+    p.layout = int(layout)
+    p.dtype = int(dtype)
+    p.aosoa_w = int(aosoa_w)
+    p.block = int(block)
+    return ripple_particles_init(p)

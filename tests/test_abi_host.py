@@ -17,7 +17,7 @@ def declared_functions():
     for header in sorted(os.listdir(os.path.join(ROOT, "include"))):
         with open(os.path.join(ROOT, "include", header)) as f:
             text = f.read()
-        decl = r"^(?:ripple_fv_status|void|const char\*)\s+(ripple_(?:fv|force2d)_[a-z_]+)\("
+        decl = r"^(?:ripple_fv_status|void|const char\*)\s+(ripple_(?:fv|force2d|particles)_[a-z_]+)\("
         names.update(re.findall(decl, text, flags=re.M))
     return sorted(names)
 
@@ -207,3 +207,25 @@ def test_force2d_reserved_must_be_zero():
     g.layout = R.SOA
     g.reserved = 1
     assert R.call("ripple_force2d_grid_init", ctypes.byref(g)) == R.E_INVALID
+
+
+# -- particle descriptors ------------------------------------------------------------
+
+def test_particles_descriptor():
+    assert ctypes.sizeof(R.Particles) == 48 and R.Particles.slots.offset == 32
+    p = R.make_particles(1000, dtype=R.F32, layout=R.SOA)
+    assert p.slots == 1024 and p.bytes == 1024 * 6 * 4
+    p = R.make_particles(1, dtype=R.F64, layout=R.AOSOA, aosoa_w=16)
+    assert p.slots == 64 and p.bytes == 64 * 6 * 8
+
+
+@pytest.mark.parametrize("bad", [
+    dict(n=0), dict(n=(1 << 34) + 1), dict(dtype=2), dict(layout=3), dict(layout=R.SOA, aosoa_w=16),
+    dict(layout=R.AOSOA, aosoa_w=8), dict(block=96),
+])
+def test_particles_rejects(bad):
+    kw = dict(n=100)
+    kw.update(bad)
+    with pytest.raises(R.RippleFVError) as e:
+        R.make_particles(**kw)
+    assert e.value.status == R.E_INVALID

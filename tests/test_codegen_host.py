@@ -14,7 +14,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, os.path.join(ROOT, "paper_2104_08571_amd"))
 
 
-@pytest.fixture(scope="module", params=["fv_kernels.hip", "force2d.hip"])
+@pytest.fixture(scope="module", params=["fv_kernels.hip", "force2d.hip", "particles.hip"])
 def assembly(request, tmp_path_factory):
     import build
     hipcc = build._hipcc()
