@@ -509,6 +509,9 @@ def main():
                     help="run only the 2D shock-bubble solver leg (prints its JSON)")
     ap.add_argument("--shock-bubble-steps", type=int, default=1000)
     ap.add_argument("--no-particles", action="store_true", help="skip the particle-update leg")
+    ap.add_argument("--particles-sizes", default="100000,1000000,10000000,20000000,40000000,80000000")
+    ap.add_argument("--particles-layouts", default="soa,aos,aosoa64")
+    ap.add_argument("--particles-dtypes", default="f32,f64")
     ap.add_argument("--particles-only", action="store_true",
                     help="run only the particle-update leg (prints its JSON)")
     ap.add_argument("--copy-only", action="store_true",
@@ -525,8 +528,8 @@ def main():
     f2_args = ([int(v) for v in args.force2d_sizes.split(",")], args.force2d_dtypes.split(","),
                args.force2d_layouts.split(","), max(args.steps, 5), args.warmup)
     sb_args = ([(6400, 4000), (9600, 6000)], ["f32", "f64"], args.shock_bubble_steps, args.warmup)
-    pt_args = ([100_000, 1_000_000, 10_000_000, 20_000_000, 40_000_000, 80_000_000],
-               ["f32", "f64"], ["soa", "aos", "aosoa64"], max(args.steps, 5), args.warmup)
+    pt_args = ([int(v) for v in args.particles_sizes.split(",")], args.particles_dtypes.split(","),
+               args.particles_layouts.split(","), max(args.steps, 5), args.warmup)
     if args.particles_only:
         print(json.dumps({"particle_update": run_particle_workload(*pt_args)}), flush=True)
         return
