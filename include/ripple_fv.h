@@ -122,8 +122,9 @@ enum ripple_fv_kernel_kind {
  *           runs 1 (2 is accepted and means 1); the fused x-y sweep always
  *           runs one cell per thread in workgroups of 512;
  *           split_xy: 0 = run the x and y sweeps as one fused pass wherever
- *           every grid of the batch allows it (16 <= n[0] <= 512, or <= 508
- *           when an x face is linked to a sub-block), 1 = always as two
+ *           every grid of the batch allows it (n[0] >= 16, and not every
+ *           grid one cell thick in z; rows longer than a workgroup are
+ *           processed in chunks), 1 = always as two
  *           separate sweeps
  *  reserved must be 0
  *  x_origin OUT: padded x index of interior cell x = 0 (see below)
@@ -245,9 +246,10 @@ ripple_fv_status ripple_fv_step(ripple_fv_ctx* ctx, const ripple_fv_grid* g, voi
  * flags: ripple_fv_run_flags.  The first call for a given set of grid
  * descriptors builds and caches a plan (workspaces, tile lists, graphs);
  * later calls with the same descriptors allocate nothing.  When every grid
- * is one cell thick in z and the x and y sweeps run separately, a step is
- * x (u -> work) and y (work -> u) only: the z sweep would change nothing,
- * and the y sweep reduces the next step's wave speeds instead. */
+ * is one cell thick in z, a step is x (u -> work) and y (work -> u) only:
+ * the z sweep would change nothing, and the y sweep reduces the next step's
+ * wave speeds instead (such grids always run the x and y sweeps
+ * separately). */
 ripple_fv_status ripple_fv_run_batch(ripple_fv_ctx* ctx, int32_t n, const ripple_fv_grid* grids,
                                      void* const* u, void* const* work, int32_t nsteps,
                                      double cfl, int32_t flags, void* stream);

@@ -384,28 +384,36 @@ hipError_t launch_force2d_dtype(int lay, const F2Params& p, int block, hipStream
 constexpr int64_t F2_MAX_EXTENT = int64_t(1) << 20;
 constexpr int64_t F2_MAX_BYTES = int64_t(1) << 46;
 
-ripple_fv_status grid2_check(const ripple_force2d_grid& g, int64_t* pitch, int64_t* bytes,
-                             int32_t* x_origin, std::string* why) {
+// Why a descriptor's inputs are invalid, or nullptr.
+const char* grid2_invalid(const ripple_force2d_grid& g) {
   for (int d = 0; d < 2; ++d) {
-    if (g.n[d] < 1 || g.n[d] > F2_MAX_EXTENT) return *why = "extent out of range [1, 2^20]", RIPPLE_FV_E_INVALID;
+    if (g.n[d] < 1 || g.n[d] > F2_MAX_EXTENT) return "extent out of range [1, 2^20]";
     if (g.bc[d] != RIPPLE_FV_TRANSMISSIVE && g.bc[d] != RIPPLE_FV_PERIODIC &&
         g.bc[d] != RIPPLE_FORCE2D_PADDED)
-      return *why = "unknown boundary kind", RIPPLE_FV_E_INVALID;
+      return "unknown boundary kind";
   }
-  if (g.dtype != RIPPLE_FV_F32 && g.dtype != RIPPLE_FV_F64) return *why = "unknown dtype", RIPPLE_FV_E_INVALID;
+  if (g.dtype != RIPPLE_FV_F32 && g.dtype != RIPPLE_FV_F64) return "unknown dtype";
   if (g.layout == RIPPLE_FV_AOSOA) {
-    if (g.aosoa_w != 16 && g.aosoa_w != 32 && g.aosoa_w != 64)
-      return *why = "aosoa_w must be 16, 32 or 64", RIPPLE_FV_E_INVALID;
+    if (g.aosoa_w != 16 && g.aosoa_w != 32 && g.aosoa_w != 64) return "aosoa_w must be 16, 32 or 64";
   } else if (g.layout == RIPPLE_FV_AOS || g.layout == RIPPLE_FV_SOA) {
-    if (g.aosoa_w != 0) return *why = "aosoa_w must be 0 unless the layout is AOSOA", RIPPLE_FV_E_INVALID;
+    if (g.aosoa_w != 0) return "aosoa_w must be 0 unless the layout is AOSOA";
   } else {
-    return *why = "unknown layout", RIPPLE_FV_E_INVALID;
+    return "unknown layout";
   }
   if (g.block != 0 && g.block != 64 && g.block != 128 && g.block != 256 && g.block != 512 &&
       g.block != 1024)
-    return *why = "block must be 0, 64, 128, 256, 512 or 1024", RIPPLE_FV_E_INVALID;
-  if (g.segment < 0) return *why = "segment < 0", RIPPLE_FV_E_INVALID;
-  if (g.reserved != 0) return *why = "reserved must be 0", RIPPLE_FV_E_INVALID;
+    return "block must be 0, 64, 128, 256, 512 or 1024";
+  if (g.segment < 0) return "segment < 0";
+  if (g.reserved != 0) return "reserved must be 0";
+  return nullptr;
+}
+
+ripple_fv_status grid2_check(const ripple_force2d_grid& g, int64_t* pitch, int64_t* bytes,
+                             int32_t* x_origin, std::string* why) {
+  if (const char* bad = grid2_invalid(g)) {
+    *why = bad;
+    return RIPPLE_FV_E_INVALID;
+  }
   const int64_t s = g.dtype == RIPPLE_FV_F32 ? 4 : 8;
   int64_t ox, px;
   if (g.layout == RIPPLE_FV_AOS) {
@@ -420,7 +428,10 @@ ripple_fv_status grid2_check(const ripple_force2d_grid& g, int64_t* pitch, int64
   const int64_t py = (int64_t)g.n[1] + 2;
   const int64_t slots = (px * py + ox + 63) / 64 * 64;
   const int64_t b = slots * NV2 * s;
-  if (b > F2_MAX_BYTES) return *why = "buffer above 2^46 bytes", RIPPLE_FV_E_INVALID;
+  if (b > F2_MAX_BYTES) {
+    *why = "buffer above 2^46 bytes";
+    return RIPPLE_FV_E_INVALID;
+  }
   pitch[0] = px;
   pitch[1] = py;
   *bytes = b;

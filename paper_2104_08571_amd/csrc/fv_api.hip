@@ -32,6 +32,8 @@ struct Plan {
   Tiling tl{};
   std::vector<ripple_fv_grid> grids;
   bool fused = false;                   // x and y sweeps as one pass
+  int seg_xy = 0;                       // rows per tile of the fused pass
+  bool chunked = false;                 // some grid's rows are cut into chunks
   bool planar = false;                  // separate sweeps, every grid one cell thick in z
   // the step returns the state to its first buffer (else the separate sweeps
   // alternate the two buffers from step to step)
@@ -313,13 +315,32 @@ ripple_fv_status build_plan(ripple_fv_ctx* ctx, int n, const ripple_fv_grid* gri
   P->lay = lay_of(grids[0]);
   P->tl = tiling_of(grids[0]);
   P->grids.assign(grids, grids + n);
-  P->fused = !P->tl.split_xy;
-  for (int g = 0; g < n; ++g) P->fused = P->fused && xy_eligible(grids[g]);
-  P->planar = !P->fused;
+  // Grids one cell thick in z run the x and y sweeps separately and skip
+  // the z sweep (the y sweep reduces the next step's wave speeds).  A fused
+  // pass there would be the whole step and would have to reduce the wave
+  // speeds itself: measured on 6400 x 4000 cells such a pass took twice the
+  // time of the two separate sweeps in FP32 (the reduction raises its
+  // register use past two workgroups per CU) and was no faster in FP64.
+  P->planar = true;
   for (int g = 0; g < n; ++g) P->planar = P->planar && grids[g].n[2] == 1;
+  P->fused = !P->tl.split_xy && !P->planar;
+  for (int g = 0; g < n; ++g) P->fused = P->fused && xy_eligible(grids[g]);
+  // The fused pass marches tiles of seg_xy rows along y.  Where that leaves
+  // fewer than XY_MIN_TILES tiles (thin or two-dimensional grids) the
+  // segments shrink, down to 16 rows (or the configured segment if that is
+  // shorter), so that the launch fills the device.
+  P->seg_xy = P->tl.yz_segment;
+  for (int g = 0; g < n; ++g) P->chunked = P->chunked || (P->fused && xy_chunked(grids[g]));
+  if (P->fused) {
+    int64_t tiles = 0;
+    for (int g = 0; g < n; ++g) tiles += tiles_xy(grids[g], P->seg_xy);
+    if (tiles < XY_MIN_TILES)
+      P->seg_xy = (int)std::max<int64_t>(std::min(16, P->seg_xy),
+                                         (int64_t)P->seg_xy * tiles / XY_MIN_TILES);
+  }
   for (int k = 0; k < 5; ++k) P->tiles[k].assign(n + 1, 0);
   for (int g = 0; g < n; ++g) {
-    P->tiles[4][g + 1] = P->tiles[4][g] + (P->fused ? tiles_xy(grids[g], P->tl.yz_segment) : 0);
+    P->tiles[4][g + 1] = P->tiles[4][g] + (P->fused ? tiles_xy(grids[g], P->seg_xy) : 0);
     P->tiles[0][g + 1] = P->tiles[0][g] + tiles_x(grids[g], P->tl.x_block);
     P->tiles[1][g + 1] = P->tiles[1][g] + tiles_yz(grids[g], 1, P->tl.yz_block, P->tl.yz_segment,
                                                    P->tl.yz_cols);
@@ -495,7 +516,7 @@ struct Launcher {
 // batch's tile list, or one launch per grid).
 ripple_fv_status enqueue_sweep(ripple_fv_ctx* ctx, Plan* P, Launcher& L, int axis, int in, int out,
                                int fuse_s, bool per_grid) {
-  SweepParams sp;
+  SweepParams sp{};
   sp.w = P->work(ctx->flag);
   sp.in = in;
   sp.out = out;
@@ -525,12 +546,13 @@ ripple_fv_status enqueue_sweep(ripple_fv_ctx* ctx, Plan* P, Launcher& L, int axi
 // Enqueue the fused x-then-y sweep (plans whose grids all allow it).
 ripple_fv_status enqueue_sweep_xy(ripple_fv_ctx* ctx, Plan* P, Launcher& L, int in, int out,
                                   bool per_grid) {
-  SweepParams sp;
+  SweepParams sp{};
   sp.w = P->work(ctx->flag);
   sp.in = in;
   sp.out = out;
-  sp.seg = P->tl.yz_segment;
+  sp.seg = P->seg_xy;
   sp.fuse_s = 0;
+  sp.chunked = P->chunked ? 1 : 0;
   sp.tiles.tile_start = P->d_tiles[4];
   hipEvent_t e1 = nullptr;
   ripple_fv_status st = L.begin(RIPPLE_FV_K_SWEEP_XY, &e1);
@@ -907,7 +929,8 @@ ripple_fv_status ripple_fv_sweep(ripple_fv_ctx* ctx, const ripple_fv_grid* g, in
     const bool linked = g->nbr[0] >= 0 || g->nbr[1] >= 0 || g->nbr[2] >= 0 || g->nbr[3] >= 0;
     if (!P->fused || linked)
       return fail(ctx, RIPPLE_FV_E_UNSUPPORTED,
-                  "fused x-y sweep needs 16 <= n[0] <= 512, unlinked x and y faces and split_xy = 0");
+                  "fused x-y sweep needs n[0] >= 16, n[2] >= 2, unlinked x and y faces and "
+                  "split_xy = 0");
     return enqueue_sweep_xy(ctx, P, L, 0, 1, false);
   }
   return enqueue_sweep(ctx, P, L, axis, 0, 1, 0, false);

@@ -55,6 +55,8 @@ struct SweepParams {
   int32_t in, out;     // buffer index read / written
   int32_t seg;         // cells per thread along the sweep axis (y, z sweeps)
   int32_t fuse_s;      // accumulate wave speeds of the output (z sweep)
+  int32_t chunked;     // fused pass: some grid's rows are cut into chunks
+  int32_t pad_;
 };
 
 struct HaloTask {
@@ -80,10 +82,14 @@ int64_t tiles_x(const ripple_fv_grid& g, int x_block);
 int64_t tiles_yz(const ripple_fv_grid& g, int axis, int yz_block, int yz_segment, int yz_cols);
 int64_t tiles_ws(const ripple_fv_grid& g);
 // Fused x-then-y sweep: workgroups of XY_THREADS lanes owning whole x rows
-// (one lane per cell, plus four ghost lanes per row when an x face is linked).
+// (one lane per cell, plus four ghost lanes per row when an x face is
+// linked), or chunks of longer rows with four ghost lanes each
+// (xy_chunk_cells).
 constexpr int XY_MIN_NX = 16;
 constexpr int XY_THREADS = 512;
+constexpr int64_t XY_MIN_TILES = 2048;
 bool xy_eligible(const ripple_fv_grid& g);
+bool xy_chunked(const ripple_fv_grid& g);
 int64_t tiles_xy(const ripple_fv_grid& g, int yz_segment);
 constexpr int WS_BLOCK = 256;
 constexpr int WS_CELLS_PER_THREAD = 4;

@@ -341,7 +341,12 @@ __global__ void __launch_bounds__(256) k_sweep_yz(SweepParams p, const DevGrid* 
 // linked to a sub-block, one per padded position x = -2 .. n0+1 (P = n0 + 4)
 // so that the four ghost lanes load the padding the halo copy filled.
 // Otherwise the lanes holding cells 0, 1, n0-2, n0-1 also write the ghost
-// slots the boundary condition defines (wrap or clamp).  Per loaded row:
+// slots the boundary condition defines (wrap or clamp).  Rows longer than a
+// workgroup are cut into chunks (xy_chunk_cells), R chunk rows per tile, each
+// with four ghost lanes: inside the row they load the neighbouring chunk's
+// cells, at the row ends what the face names (clamped, wrapped or padding),
+// so every chunk reconstructs its edge faces from the same states as an
+// unbroken row.  Per loaded row:
 // publish the cells to LDS; reconstruct and publish each cell's right
 // evolved state; compute each cell's left face flux and publish it; update.
 // The ghost reconstruction and the right-most face come from the periodic
@@ -372,7 +377,9 @@ template <typename T> constexpr int xy_unroll() {
   return sizeof(T) == 4 ? RFV_XY_UNROLL_F32 : RFV_XY_UNROLL_F64;
 }
 
-template <typename T, int LAY>
+// CHUNKED: the launch holds a grid whose rows are cut into chunks (the
+// variant without it keeps the decoding of whole rows out of the loop).
+template <typename T, int LAY, bool CHUNKED>
 __global__ void __launch_bounds__(XY_THREADS) k_sweep_xy(SweepParams p,
                                                          const DevGrid* __restrict__ grids,
                                                          const int64_t* __restrict__ tile_start,
@@ -390,24 +397,35 @@ __global__ void __launch_bounds__(XY_THREADS) k_sweep_xy(SweepParams p,
     const DevGrid& G = grids[g];
     const int lt = (int)(gt - tile_start[g]);
     const int nx = G.n[0], ny = G.n[1], nz = G.n[2];
-    const bool ghost_lanes = G.mode[0] == FACE_HALO || G.mode[1] == FACE_HALO;
-    const int P = ghost_lanes ? nx + 4 : nx;      // lanes per row
-    const int R = NT / P;                          // rows per tile
+    const bool linked_x = G.mode[0] == FACE_HALO || G.mode[1] == FACE_HALO;
+    const int cw = CHUNKED ? xy_chunk_cells(nx, nz, linked_x, NT) : nx;  // cells per x chunk
+    const bool wide = cw < nx;                     // rows cut into chunks
+    const bool ghost_lanes = wide || linked_x;
+    const int nxc = CHUNKED ? (nx + cw - 1) / cw : 1;  // x chunks per row
     const int nseg = (ny + p.seg - 1) / p.seg;
-    const int chunk = lt / nseg;
-    const int s = lt - chunk * nseg;
+    const int s = lt % nseg;
+    const int rest = lt / nseg;
+    const int xch = rest % nxc;
+    const int chunk = rest / nxc;                  // chunk of R rows along z
+    const int xoff = xch * cw;                     // x of the chunk's first cell
+    const int ncx = min(nx - xoff, cw);            // cells of the chunk
+    const int P = ghost_lanes ? ncx + 4 : ncx;     // lanes per row
+    const int R = NT / (ghost_lanes ? cw + 4 : cw);  // rows per tile
     const int rs = tid / P;                        // row slot of this lane
-    const int x = tid - rs * P - (ghost_lanes ? 2 : 0);  // the lane's x (-2 .. n0+1)
+    // the lane's x relative to the chunk (-2 .. ncx+1 with ghost lanes)
+    const int xl_ = tid - rs * P - (ghost_lanes ? 2 : 0);
+    const int x = xoff + xl_;                      // ... and in the row
     const int kk = chunk * R + rs;
     const bool row_on = rs < R && kk < nz;         // the lane belongs to a row
-    const bool on = row_on && x >= 0 && x < nx;    // ... and holds an interior cell
+    const bool on = row_on && xl_ >= 0 && xl_ < ncx;  // ... and holds a cell of the chunk
     // both x faces periodic: the ghost reconstruction and the last face are
     // those of the partner cells (any other case computes them)
-    const bool periodic_x = G.mode[0] == FACE_PERIODIC && G.mode[1] == FACE_PERIODIC;
-    const int LP = nx + 4;                         // LDS row pitch
-    const int lb = (row_on ? rs : 0) * LP + 2;     // LDS slot of cell 0 of the lane's row
-    const int xl = row_on ? x : 0;                 // LDS slot the lane writes: lb + xl
-    const int xr = on ? x : 0;                     // slot whose neighbours it reads
+    const bool periodic_x =
+        !ghost_lanes && G.mode[0] == FACE_PERIODIC && G.mode[1] == FACE_PERIODIC;
+    const int LP = ncx + 4;                        // LDS row pitch
+    const int lb = (row_on ? rs : 0) * LP + 2;     // LDS slot of the chunk's cell 0 in the lane's row
+    const int xl = row_on ? xl_ : 0;               // LDS slot the lane writes: lb + xl
+    const int xr = on ? xl_ : 0;                   // slot whose neighbours it reads
     // addresses: column (x, kk) at row j is q0 + (j + 2) Px + lane offset; a
     // ghost lane reads the cell its face names (clamped, wrapped or padding)
     const int kc = row_on ? kk : chunk * R;
@@ -440,22 +458,22 @@ __global__ void __launch_bounds__(XY_THREADS) k_sweep_xy(SweepParams p,
         for (int c = 0; c < 5; ++c) sU[c][lb + xl] = u[c];
         if (on && !ghost_lanes) {
           if (periodic_x) {
-            if (x >= nx - 2) {
+            if (xl_ >= ncx - 2) {
 #pragma unroll
-              for (int c = 0; c < 5; ++c) sU[c][lb + x - nx] = u[c];
+              for (int c = 0; c < 5; ++c) sU[c][lb + xl_ - ncx] = u[c];
             }
-            if (x < 2) {
+            if (xl_ < 2) {
 #pragma unroll
-              for (int c = 0; c < 5; ++c) sU[c][lb + nx + x] = u[c];
+              for (int c = 0; c < 5; ++c) sU[c][lb + ncx + xl_] = u[c];
             }
           } else {
-            if (x == 0) {
+            if (xl_ == 0) {
 #pragma unroll
               for (int c = 0; c < 5; ++c) sU[c][lb - 1] = sU[c][lb - 2] = u[c];
             }
-            if (x == nx - 1) {
+            if (xl_ == ncx - 1) {
 #pragma unroll
-              for (int c = 0; c < 5; ++c) sU[c][lb + nx] = sU[c][lb + nx + 1] = u[c];
+              for (int c = 0; c < 5; ++c) sU[c][lb + ncx] = sU[c][lb + ncx + 1] = u[c];
             }
           }
         }
@@ -473,12 +491,12 @@ __global__ void __launch_bounds__(XY_THREADS) k_sweep_xy(SweepParams p,
       }
       if (on) {
 #pragma unroll
-        for (int c = 0; c < 5; ++c) sR[c][lb + x] = br[c];
-        if (periodic_x && x == nx - 1) {
+        for (int c = 0; c < 5; ++c) sR[c][lb + xl_] = br[c];
+        if (periodic_x && xl_ == ncx - 1) {
 #pragma unroll
           for (int c = 0; c < 5; ++c) sR[c][lb - 1] = br[c];
         }
-        if (!periodic_x && x == 0) {
+        if (!periodic_x && xl_ == 0) {
           // ghost cell -1: stencil u_{-2}, u_{-1}, u_0
           T ug[5], dm[5], dp[5], gl[5], gr[5];
 #pragma unroll
@@ -502,25 +520,25 @@ __global__ void __launch_bounds__(XY_THREADS) k_sweep_xy(SweepParams p,
       }
       if (on) {
 #pragma unroll
-        for (int c = 0; c < 5; ++c) sF[c][lb + x] = fl[c];
+        for (int c = 0; c < 5; ++c) sF[c][lb + xl_] = fl[c];
         if (periodic_x) {
-          if (x == 0) {
+          if (xl_ == 0) {
 #pragma unroll
-            for (int c = 0; c < 5; ++c) sF[c][lb + nx] = fl[c];
+            for (int c = 0; c < 5; ++c) sF[c][lb + ncx] = fl[c];
           }
-        } else if (x == nx - 1) {
+        } else if (xl_ == ncx - 1) {
           // ghost cell n0: stencil u_{n0-1}, u_{n0}, u_{n0+1}; face n0 - 1/2
           T ug[5], dm[5], dp[5], gl[5], gr[5], fg[5];
 #pragma unroll
           for (int c = 0; c < 5; ++c) {
-            ug[c] = sU[c][lb + nx];
+            ug[c] = sU[c][lb + ncx];
             dm[c] = ug[c] - u[c];
-            dp[c] = sU[c][lb + nx + 1] - ug[c];
+            dp[c] = sU[c][lb + ncx + 1] - ug[c];
           }
           hancock<T, 0>(ug, dm, dp, hlx, gl, gr);
           hllc<T, 0>(br, gl, fg);
 #pragma unroll
-          for (int c = 0; c < 5; ++c) sF[c][lb + nx] = fg[c];
+          for (int c = 0; c < 5; ++c) sF[c][lb + ncx] = fg[c];
         }
       }
       __syncthreads();
@@ -901,21 +919,24 @@ int64_t tiles_yz(const ripple_fv_grid& g, int axis, int yz_block, int yz_segment
   return nchunk * nseg;
 }
 
-// Lanes per x row in the fused sweep: one per cell, or one per padded
-// position when an x face is linked to a sub-block.
-static int xy_row_lanes(const ripple_fv_grid& g) {
-  return (g.nbr[0] >= 0 || g.nbr[1] >= 0) ? g.n[0] + 4 : g.n[0];
-}
+// Tiles of the fused sweep (must match the kernel's decoding): rows, or
+// chunks of longer rows (xy_chunk_cells), of R at consecutive z per tile.
+bool xy_eligible(const ripple_fv_grid& g) { return g.n[0] >= XY_MIN_NX; }
 
-bool xy_eligible(const ripple_fv_grid& g) {
-  return g.n[0] >= XY_MIN_NX && xy_row_lanes(g) <= XY_THREADS;
+bool xy_chunked(const ripple_fv_grid& g) {
+  const bool linked = g.nbr[0] >= 0 || g.nbr[1] >= 0;
+  return xy_chunk_cells(g.n[0], g.n[2], linked, XY_THREADS) < g.n[0];
 }
 
 int64_t tiles_xy(const ripple_fv_grid& g, int yz_segment) {
-  const int64_t rows = XY_THREADS / xy_row_lanes(g);
+  const bool linked = g.nbr[0] >= 0 || g.nbr[1] >= 0;
+  const int cw = xy_chunk_cells(g.n[0], g.n[2], linked, XY_THREADS);
+  const bool ghost = linked || cw < g.n[0];
+  const int64_t rows = XY_THREADS / (ghost ? cw + 4 : cw);
+  const int64_t nxc = (g.n[0] + cw - 1) / cw;
   const int64_t nchunk = (g.n[2] + rows - 1) / rows;
   const int64_t nseg = (g.n[1] + yz_segment - 1) / yz_segment;
-  return nchunk * nseg;
+  return nchunk * nxc * nseg;
 }
 
 int64_t tiles_ws(const ripple_fv_grid& g) {
@@ -983,8 +1004,12 @@ hipError_t launch_sweep(int dtype, int lay, int axis, const Tiling& tl, const Sw
 
 template <typename T, int LAY>
 static hipError_t sweep_xy_typed(const Tiling&, const SweepParams& p, int blocks, hipStream_t s) {
-  hipLaunchKernelGGL((k_sweep_xy<T, LAY>), dim3(blocks), dim3(XY_THREADS), 0, s, p, p.w.grids,
-                     p.tiles.tile_start, p.w.lam);
+  if (p.chunked)
+    hipLaunchKernelGGL((k_sweep_xy<T, LAY, true>), dim3(blocks), dim3(XY_THREADS), 0, s, p,
+                       p.w.grids, p.tiles.tile_start, p.w.lam);
+  else
+    hipLaunchKernelGGL((k_sweep_xy<T, LAY, false>), dim3(blocks), dim3(XY_THREADS), 0, s, p,
+                       p.w.grids, p.tiles.tile_start, p.w.lam);
   return hipGetLastError();
 }
 

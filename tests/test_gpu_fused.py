@@ -4,7 +4,8 @@ for sub-blocks linked along x and/or y (whose padding, corners included,
 the halo copies fill before the pass); grids it does not accept (rows
 outside 16..512 cells) fall back to the separate sweeps with the same
 results.  Also checks the in-place semantics of the step entry points on
-both paths."""
+both paths.  Rows longer than a workgroup run fused in chunks of 508
+cells with ghost lanes, also bitwise equal to the separate sweeps."""
 import numpy as np
 import pytest
 import torch
@@ -38,12 +39,13 @@ def test_fused_equals_split(dtype, layout, w, cols):
         assert np.array_equal(Uf, Us), (shape, bc)
 
 
-@pytest.mark.parametrize("nx", [2, 3, 16, 17, 56, 57, 58, 59, 60, 61, 62, 255, 512, 520, 1000])
+@pytest.mark.parametrize("nx", [2, 3, 16, 17, 56, 57, 58, 59, 60, 61, 62, 255, 508, 509, 512, 513,
+                                520, 1000, 1016, 1017, 1100])
 def test_fused_row_lengths(nx):
-    """Row lengths from 2 to 1000 cells: below, inside and above what one
-    workgroup holds (fused where 16 <= n0 <= 512, separate sweeps
-    otherwise), odd lengths; blast (transmissive) vs periodic faces; several
-    z planes per tile."""
+    """Row lengths from 2 to 1100 cells: below, inside and above what one
+    workgroup holds (fused where n0 >= 16, in chunks of 508 cells above 512,
+    separate sweeps below 16), odd lengths; blast (transmissive) vs periodic
+    faces; several z planes per tile."""
     shape = (nx, 9, 7)
     for bc in ((1, 1, 1), (0, 0, 0)):
         # the blast needs a few cells across it to stay physical
@@ -79,6 +81,31 @@ def test_linked_sub_blocks_match_whole_grid():
     with pytest.raises(R.RippleFVError) as e:
         R.ripple_fv_sweep(G.ctx(), sub, R.AXIS_XY, a.data_ptr(), b.data_ptr(), 1e-3, G.stream())
     assert e.value.status == R.E_UNSUPPORTED
+
+
+def test_wide_rows_linked_sub_blocks_match_whole_grid():
+    """Rows cut into chunks, on a whole grid and on sub-blocks whose linked x
+    faces fall inside a chunk or at its edge: bitwise the whole grid."""
+    shape = (1100, 20, 6)
+    whole = R.make_grid(shape, dtype=R.F32, layout=R.SOA, bc=(1, 0, 1))
+    W = ist.smooth_periodic(shape, seed=88)
+    (ref,), (t_ref,) = G.run(whole, W, 3)
+    split = R.copy_grid(whole, split_xy=1)
+    (ref_s,), _ = G.run(split, W, 3)
+    assert np.array_equal(ref, ref_s)
+    for parts in ((2, 1, 1), (2, 2, 1), (3, 1, 2)):
+        subs = R.ripple_fv_partition(whole, parts)
+        states, origins = [], []
+        for idx, sb in enumerate(subs):
+            a, b, c = idx % parts[0], (idx // parts[0]) % parts[1], idx // (parts[0] * parts[1])
+            o = [k * (n // m) + min(k, n % m) for k, n, m in zip((a, b, c), shape, parts)]
+            origins.append(o)
+            states.append(ist.smooth_periodic(list(sb.n), 88, origin=o, n_global=shape))
+        outs, ts = G.run(subs, states, 3)
+        for sb, U, o, t in zip(subs, outs, origins, ts):
+            assert t == t_ref
+            part = ref[:, o[2]:o[2] + sb.n[2], o[1]:o[1] + sb.n[1], o[0]:o[0] + sb.n[0]]
+            assert np.array_equal(U, part), (parts, o)
 
 
 @pytest.mark.parametrize("dtype", [R.F32, R.F64], ids=["f32", "f64"])

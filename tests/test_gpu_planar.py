@@ -6,10 +6,10 @@ and 9600 x 6000 cells).
 A sweep along a one-cell axis reads the same state on both faces of every
 cell and changes nothing, so a grid with n[2] = 1 is a 2D problem; with
 dx[2] large the z wave speed never sets dt, which then equals the 2D
-solver's dt = CFL min(dx / S_x, dy / S_y).  Where the x and y sweeps run
-separately the library skips the z sweep altogether (the y sweep reduces
-the next step's wave speeds); the fused path keeps it.  Parity is against
-the FP64 oracle, which runs the full three-sweep step.
+solver's dt = CFL min(dx / S_x, dy / S_y).  The library runs the x and y
+sweeps separately on such grids and skips the z sweep: the y sweep reduces
+the next step's wave speeds.  Parity is against the FP64 oracle, which runs
+the full three-sweep step.
 """
 import numpy as np
 import pytest
@@ -61,38 +61,48 @@ def test_one_cell_axes_match_oracle(oracle, dtype, shape, bc, split):
 
 
 @pytest.mark.parametrize("dtype", [R.F32, R.F64], ids=["f32", "f64"])
-def test_planar_skip_equals_fused_with_z(dtype):
-    """Separate sweeps without z (planar path) and the fused pass with its z
-    sweep give the same bits, for 1, 2 and 5 steps, eager and graph."""
-    shape = (48, 40, 1)
-    W = ist.smooth_periodic(shape, seed=33)
-    out = {}
-    for split in (0, 1):
-        g = R.make_grid(shape, dtype=dtype, layout=R.SOA, bc=(1, 0, 1),
-                        tiling=(0, 0, 0, 0, 0, split))
+def test_planar_equals_two_identical_planes(dtype):
+    """A planar grid (separate x and y sweeps, no z sweep) and the same state
+    on two identical periodic z planes (fused x-y pass and a z sweep that
+    changes nothing) give the same bits in every plane, for 1, 2 and 5
+    steps: rows inside one workgroup and rows cut into chunks."""
+    for nx, ny in ((48, 40), (1100, 12)):
+        W1 = ist.smooth_periodic((nx, ny, 1), seed=33)
+        W2 = torch.cat([W1, W1], dim=1)
+        g1 = R.make_grid((nx, ny, 1), dtype=dtype, layout=R.SOA, bc=(1, 0, 1),
+                         dx=(1.0 / nx, 1.0 / ny, 1.0))
+        g2 = R.make_grid((nx, ny, 2), dtype=dtype, layout=R.SOA, bc=(1, 0, 1),
+                         dx=(1.0 / nx, 1.0 / ny, 1.0))
         for n in (1, 2, 5):
-            for flags in (R.RUN_EAGER, R.RUN_GRAPH):
-                out[(split, n, flags)] = G.run(g, W, n, flags=flags)
-    for n in (1, 2, 5):
-        for flags in (R.RUN_EAGER, R.RUN_GRAPH):
-            (a,), ta = out[(0, n, flags)]
-            (b,), tb = out[(1, n, flags)]
-            assert ta == tb and np.array_equal(a, b), (n, flags)
+            (a,), ta = G.run(g1, W1, n)
+            (b,), tb = G.run(g2, W2, n, flags=R.RUN_GRAPH)
+            assert ta == tb, (nx, n)
+            assert np.array_equal(b[:, :1], a) and np.array_equal(b[:, 1:], a), (nx, n)
 
 
-def test_planar_graph_step_counts():
-    shape = (600, 40, 1)   # rows longer than one workgroup: separate sweeps
+@pytest.mark.parametrize("split", [0, 1])
+def test_planar_graph_step_counts(split):
+    """Graph replays equal the eager loop for odd and even step counts, with
+    and without split_xy set (planar grids run separate sweeps either way)."""
+    shape = (600, 40, 1)   # rows longer than one workgroup
     W = ist.smooth_periodic(shape, seed=34)
-    g = R.make_grid(shape, dtype=R.F32, layout=R.SOA, bc=(1, 1, 1))
-    for n in (1, 3, 67):
+    g = R.make_grid(shape, dtype=R.F32, layout=R.SOA, bc=(1, 1, 1),
+                    tiling=(0, 0, 0, 0, 0, split))
+    for n in (1, 3, 67, 2):
         (a,), ta = G.run(g, W, n)
         (b,), tb = G.run(g, W, n, flags=R.RUN_GRAPH)
         assert ta == tb and np.array_equal(a, b), n
+    a_, b_ = G.load(g, W), G.buffer(g)
+    R.ripple_fv_step(G.ctx(), g, a_.data_ptr(), b_.data_ptr(), 0.9, 0.0, None, G.stream())
+    (one,), _ = G.run(g, W, 1)
+    assert np.array_equal(G.export(g, a_), one)      # ripple_fv_step leaves the state in u
 
 
-def test_planar_partition_matches_whole():
+@pytest.mark.parametrize("split", [0, 1])
+def test_planar_partition_matches_whole(split):
     shape = (64, 48, 1)
-    whole = R.make_grid(shape, dtype=R.F64, layout=R.SOA, bc=(0, 1, 1), tiling=(0, 0, 0, 0, 0, 1))
+    whole = R.make_grid(shape, dtype=R.F64, layout=R.SOA, bc=(0, 1, 1),
+                        tiling=(0, 0, 0, 0, 0, split))
     W = ist.smooth_periodic(shape, seed=35)
     (ref,), (t_ref,) = G.run(whole, W, 4)
     parts = (2, 2, 1)
