@@ -490,7 +490,8 @@ def main():
     ap.add_argument("--layout", default="soa", choices=["soa", "aos", "aosoa16", "aosoa32", "aosoa64"])
     ap.add_argument("--tiling", default="0,0,0,0,0,0",
                     help="x_block,yz_block,yz_segment,persist,yz_cols,split_xy "
-                         "(0 = library default; split_xy 1 = separate x and y sweeps)")
+                         "(0 = library default; split_xy 1 = separate x and y sweeps, "
+                         "2 / 3 = fused pass in the rows / wave-strip form)")
     ap.add_argument("--no-f64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--cpu-steps", type=int, default=1,
                     help="oracle steps timed for cpu_baseline (0 = skip)")

@@ -121,11 +121,15 @@ enum ripple_fv_kernel_kind {
  *           sweeps (1, 2; 0 = 2 for FP32 SoA/AoSoA, else 1); FP64 always
  *           runs 1 (2 is accepted and means 1); the fused x-y sweep always
  *           runs one cell per thread in workgroups of 512;
- *           split_xy: 0 = run the x and y sweeps as one fused pass wherever
- *           every grid of the batch allows it (n[0] >= 16, and not every
- *           grid one cell thick in z; rows longer than a workgroup are
- *           processed in chunks), 1 = always as two
- *           separate sweeps
+ *           split_xy: how the x and y sweeps run.  0 = as one fused pass
+ *           wherever every grid of the batch allows it (n[0] >= 16, and not
+ *           every grid one cell thick in z), in the form that occupies fewer
+ *           vector lanes per cell by a measured cost model: whole rows per
+ *           workgroup with neighbours exchanged through LDS, or strips of 60
+ *           cells per wave with neighbours exchanged by lane shifts (any row
+ *           length); 1 = always as two separate sweeps; 2 = fused, whole
+ *           rows where every row fits a workgroup of 512 lanes (n[0] <= 512,
+ *           508 with a linked x face), else strips; 3 = fused, strips
  *  reserved must be 0
  *  x_origin OUT: padded x index of interior cell x = 0 (see below)
  *  pitch, bytes   OUT: padded extents (Px, Py, Pz) and bytes of one buffer

@@ -104,33 +104,6 @@ __device__ __forceinline__ void store_row(void* buf, int64_t q0, int64_t ctot, u
   }
 }
 
-// Whole-wave lane shifts (DPP wave_shr:1 / wave_shl:1): lane l receives the
-// value of lane l - 1 (from_below) or l + 1 (from_above); the end lanes keep
-// their own value and only ever feed discarded results.
-__device__ __forceinline__ float from_below(float v) {
-  const int i = __builtin_bit_cast(int, v);
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(i, i, 0x138, 0xF, 0xF, false));
-}
-__device__ __forceinline__ float from_above(float v) {
-  const int i = __builtin_bit_cast(int, v);
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(i, i, 0x130, 0xF, 0xF, false));
-}
-__device__ __forceinline__ double shift64(double v, int ctrl_below) {
-  const uint64_t u = __builtin_bit_cast(uint64_t, v);
-  const int lo = (int)(uint32_t)u, hi = (int)(uint32_t)(u >> 32);
-  uint32_t a, b;
-  if (ctrl_below) {
-    a = (uint32_t)__builtin_amdgcn_update_dpp(lo, lo, 0x138, 0xF, 0xF, false);
-    b = (uint32_t)__builtin_amdgcn_update_dpp(hi, hi, 0x138, 0xF, 0xF, false);
-  } else {
-    a = (uint32_t)__builtin_amdgcn_update_dpp(lo, lo, 0x130, 0xF, 0xF, false);
-    b = (uint32_t)__builtin_amdgcn_update_dpp(hi, hi, 0x130, 0xF, 0xF, false);
-  }
-  return __builtin_bit_cast(double, ((uint64_t)b << 32) | a);
-}
-__device__ __forceinline__ double from_below(double v) { return shift64(v, 1); }
-__device__ __forceinline__ double from_above(double v) { return shift64(v, 0); }
-
 // Physical fluxes of one state along x (F) and y (G), sharing 1/rho and p:
 //   F = (m_x, m_x u + p, m_y u, u (E + p)),  G = (m_y, m_x v, m_y v + p, v (E + p)),
 //   p = (gamma - 1) E - ((gamma - 1)/2) |m|^2 / rho.

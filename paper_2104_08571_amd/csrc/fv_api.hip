@@ -33,7 +33,7 @@ struct Plan {
   std::vector<ripple_fv_grid> grids;
   bool fused = false;                   // x and y sweeps as one pass
   int seg_xy = 0;                       // rows per tile of the fused pass
-  bool chunked = false;                 // some grid's rows are cut into chunks
+  int xmode = XM_ROWS;                  // form of the fused pass
   bool planar = false;                  // separate sweeps, every grid one cell thick in z
   // the step returns the state to its first buffer (else the separate sweeps
   // alternate the two buffers from step to step)
@@ -150,7 +150,7 @@ ripple_fv_status grid_check(const ripple_fv_grid* g, int64_t pitch[3], int64_t* 
   if (!valid_block(g->x_block, {0, 128, 256}) || !valid_block(g->yz_block, {0, 64, 128, 256}) ||
       g->yz_segment < 0 || (g->yz_segment > 0 && g->yz_segment < 4) || g->yz_segment > 4096 ||
       g->persist < 0 || g->persist > 64 || !valid_block(g->yz_cols, {0, 1, 2}) ||
-      !valid_block(g->split_xy, {0, 1}) || g->reserved != 0) {
+      !valid_block(g->split_xy, {0, 1, 2, 3}) || g->reserved != 0) {
     *why = "bad tiling knobs";
     return RIPPLE_FV_E_INVALID;
   }
@@ -323,24 +323,24 @@ ripple_fv_status build_plan(ripple_fv_ctx* ctx, int n, const ripple_fv_grid* gri
   // register use past two workgroups per CU) and was no faster in FP64.
   P->planar = true;
   for (int g = 0; g < n; ++g) P->planar = P->planar && grids[g].n[2] == 1;
-  P->fused = !P->tl.split_xy && !P->planar;
+  P->fused = P->tl.split_xy != 1 && !P->planar;
   for (int g = 0; g < n; ++g) P->fused = P->fused && xy_eligible(grids[g]);
   // The fused pass marches tiles of seg_xy rows along y.  Where that leaves
   // fewer than XY_MIN_TILES tiles (thin or two-dimensional grids) the
   // segments shrink, down to 16 rows (or the configured segment if that is
   // shorter), so that the launch fills the device.
   P->seg_xy = P->tl.yz_segment;
-  for (int g = 0; g < n; ++g) P->chunked = P->chunked || (P->fused && xy_chunked(grids[g]));
+  if (P->fused) P->xmode = xy_mode(P->dtype, grids, n, P->tl.split_xy);
   if (P->fused) {
     int64_t tiles = 0;
-    for (int g = 0; g < n; ++g) tiles += tiles_xy(grids[g], P->seg_xy);
+    for (int g = 0; g < n; ++g) tiles += tiles_xy(grids[g], P->seg_xy, P->xmode);
     if (tiles < XY_MIN_TILES)
       P->seg_xy = (int)std::max<int64_t>(std::min(16, P->seg_xy),
                                          (int64_t)P->seg_xy * tiles / XY_MIN_TILES);
   }
   for (int k = 0; k < 5; ++k) P->tiles[k].assign(n + 1, 0);
   for (int g = 0; g < n; ++g) {
-    P->tiles[4][g + 1] = P->tiles[4][g] + (P->fused ? tiles_xy(grids[g], P->seg_xy) : 0);
+    P->tiles[4][g + 1] = P->tiles[4][g] + (P->fused ? tiles_xy(grids[g], P->seg_xy, P->xmode) : 0);
     P->tiles[0][g + 1] = P->tiles[0][g] + tiles_x(grids[g], P->tl.x_block);
     P->tiles[1][g + 1] = P->tiles[1][g] + tiles_yz(grids[g], 1, P->tl.yz_block, P->tl.yz_segment,
                                                    P->tl.yz_cols);
@@ -552,7 +552,7 @@ ripple_fv_status enqueue_sweep_xy(ripple_fv_ctx* ctx, Plan* P, Launcher& L, int 
   sp.out = out;
   sp.seg = P->seg_xy;
   sp.fuse_s = 0;
-  sp.chunked = P->chunked ? 1 : 0;
+  sp.xmode = P->xmode;
   sp.tiles.tile_start = P->d_tiles[4];
   hipEvent_t e1 = nullptr;
   ripple_fv_status st = L.begin(RIPPLE_FV_K_SWEEP_XY, &e1);
@@ -930,7 +930,7 @@ ripple_fv_status ripple_fv_sweep(ripple_fv_ctx* ctx, const ripple_fv_grid* g, in
     if (!P->fused || linked)
       return fail(ctx, RIPPLE_FV_E_UNSUPPORTED,
                   "fused x-y sweep needs n[0] >= 16, n[2] >= 2, unlinked x and y faces and "
-                  "split_xy = 0");
+                  "split_xy != 1");
     return enqueue_sweep_xy(ctx, P, L, 0, 1, false);
   }
   return enqueue_sweep(ctx, P, L, axis, 0, 1, 0, false);
@@ -1231,7 +1231,7 @@ extern "C" ripple_fv_status ripple_fv_batch_tune(ripple_fv_ctx* ctx, int32_t n,
     if (st || base[0].dtype == RIPPLE_FV_F64) break;  // FP64 runs one cell per thread
     st = consider(with([&](ripple_fv_grid& g) { g.yz_cols = cols; }));
   }
-  for (int split : {0, 1}) {
+  for (int split : {0, 1, 2, 3}) {
     if (st) break;
     st = consider(with([&](ripple_fv_grid& g) { g.split_xy = split; }));
   }

@@ -73,25 +73,4 @@ RFV_HD int64_t xcd_order(int64_t b, int64_t nblocks) {
   return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
 }
 
-// Cells per x chunk of the fused x-y pass for rows of nx cells in nz planes
-// (lanes per row: nx, or nx + 4 with a linked x face).  Rows that fit a
-// workgroup of `threads` lanes stay whole (the result is nx); longer rows are
-// cut into chunks of threads / r - 4 cells plus 4 ghost lanes, r in {1, 2,
-// 4} chunk rows at consecutive z per workgroup (r <= nz), choosing the r that
-// needs the fewest workgroups (ties: the longer chunk).
-RFV_HD int xy_chunk_cells(int nx, int nz, bool linked, int threads) {
-  if ((linked ? nx + 4 : nx) <= threads) return nx;
-  int best = threads - 4;
-  int64_t best_tiles = -1;
-  for (int r = 1; r <= 4 && (r == 1 || r <= nz); r *= 2) {
-    const int c = threads / r - 4;
-    const int64_t tiles = (int64_t)((nx + c - 1) / c) * ((nz + r - 1) / r);
-    if (best_tiles < 0 || tiles < best_tiles) {
-      best_tiles = tiles;
-      best = c;
-    }
-  }
-  return best;
-}
-
 }  // namespace rfv

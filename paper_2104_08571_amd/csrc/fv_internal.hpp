@@ -55,7 +55,7 @@ struct SweepParams {
   int32_t in, out;     // buffer index read / written
   int32_t seg;         // cells per thread along the sweep axis (y, z sweeps)
   int32_t fuse_s;      // accumulate wave speeds of the output (z sweep)
-  int32_t chunked;     // fused pass: some grid's rows are cut into chunks
+  int32_t xmode;       // fused pass: XM_ROWS or XM_WAVES
   int32_t pad_;
 };
 
@@ -72,7 +72,7 @@ struct Tiling {
   int yz_segment;  // cells per thread along y/z
   int persist;     // workgroups per CU for persistent launches, 0 = one per tile
   int yz_cols;     // adjacent x cells per thread in the y/z sweeps (1 or 2)
-  int split_xy;    // 1: separate x and y sweeps even where they could be fused
+  int split_xy;    // 1: separate x and y sweeps; 2, 3: fused, rows / wave-strip form
 };
 
 int lay_of(const ripple_fv_grid& g);
@@ -81,16 +81,25 @@ int lay_of(const ripple_fv_grid& g);
 int64_t tiles_x(const ripple_fv_grid& g, int x_block);
 int64_t tiles_yz(const ripple_fv_grid& g, int axis, int yz_block, int yz_segment, int yz_cols);
 int64_t tiles_ws(const ripple_fv_grid& g);
-// Fused x-then-y sweep: workgroups of XY_THREADS lanes owning whole x rows
-// (one lane per cell, plus four ghost lanes per row when an x face is
-// linked), or chunks of longer rows with four ghost lanes each
-// (xy_chunk_cells).
+// Fused x-then-y sweep, in one of two forms of the x exchange:
+//  XM_ROWS   workgroups of XY_THREADS lanes owning whole x rows (one lane per
+//            cell, plus four ghost lanes per row when an x face is linked),
+//            neighbours exchanged through LDS (three barriers per row);
+//  XM_WAVES  every wave owns a strip of XY_WAVE_CELLS cells of one row plus
+//            two ghost lanes on each side and exchanges neighbours by lane
+//            shifts: no LDS and no barriers, any row length.
+constexpr int XM_ROWS = 0, XM_WAVES = 1;
 constexpr int XY_MIN_NX = 16;
 constexpr int XY_THREADS = 512;
+constexpr int XY_WAVE_CELLS = 60;
+constexpr int XY_WAVE_THREADS = 256;   // workgroup of the wave-strip form
 constexpr int64_t XY_MIN_TILES = 2048;
 bool xy_eligible(const ripple_fv_grid& g);
-bool xy_chunked(const ripple_fv_grid& g);
-int64_t tiles_xy(const ripple_fv_grid& g, int yz_segment);
+// Form of the fused pass for a batch of grids of precision dtype and the
+// split_xy knob (0: cheaper form by the cost model, 2: rows where every row
+// fits a workgroup, 3: wave strips).
+int xy_mode(int dtype, const ripple_fv_grid* grids, int n, int split_xy);
+int64_t tiles_xy(const ripple_fv_grid& g, int yz_segment, int xmode);
 constexpr int WS_BLOCK = 256;
 constexpr int WS_CELLS_PER_THREAD = 4;
 

@@ -336,21 +336,28 @@ __global__ void __launch_bounds__(256) k_sweep_yz(SweepParams p, const DevGrid* 
 // of k_sweep_x followed by k_sweep_yz along y, so the result is bitwise that
 // of the two separate kernels.
 //
-// Tile = (R whole x rows at consecutive z) x (segment of p.seg rows along
-// y).  A row takes P lanes: one per cell (P = n0), or, when an x face is
-// linked to a sub-block, one per padded position x = -2 .. n0+1 (P = n0 + 4)
-// so that the four ghost lanes load the padding the halo copy filled.
-// Otherwise the lanes holding cells 0, 1, n0-2, n0-1 also write the ghost
-// slots the boundary condition defines (wrap or clamp).  Rows longer than a
-// workgroup are cut into chunks (xy_chunk_cells), R chunk rows per tile, each
-// with four ghost lanes: inside the row they load the neighbouring chunk's
-// cells, at the row ends what the face names (clamped, wrapped or padding),
-// so every chunk reconstructs its edge faces from the same states as an
-// unbroken row.  Per loaded row:
-// publish the cells to LDS; reconstruct and publish each cell's right
+// Two forms of the x exchange (XM):
+//
+// XM_ROWS.  Tile = (R whole x rows at consecutive z) x (segment of p.seg
+// rows along y).  A row takes P lanes: one per cell (P = n0), or, when an x
+// face is linked to a sub-block, one per padded position x = -2 .. n0+1
+// (P = n0 + 4) so that the four ghost lanes load the padding the halo copy
+// filled.  Otherwise the lanes holding cells 0, 1, n0-2, n0-1 also write the
+// ghost slots the boundary condition defines (wrap or clamp).  Per loaded
+// row: publish the cells to LDS; reconstruct and publish each cell's right
 // evolved state; compute each cell's left face flux and publish it; update.
 // The ghost reconstruction and the right-most face come from the periodic
 // partner cell, or are computed by the edge lane otherwise.
+//
+// XM_WAVES.  Every wave owns a strip of up to XY_WAVE_CELLS cells of one row
+// and a y segment; its 64 lanes hold the positions x = x0-2 .. x0+61, and
+// the four outside the strip (ghost lanes) load the cells their positions
+// name: the neighbouring strips' cells inside the row, at its ends what the
+// face names (clamped, wrapped or padding).  Neighbours are read by whole-wave
+// lane shifts, so waves are independent (no LDS, no barriers) and a row may
+// have any length; every lane runs the whole x sweep and the strip's cells
+// take exactly the arithmetic of an unbroken row.  The workgroup's waves take
+// consecutive (z, strip) pairs in row-major order.
 //
 // Rows outside the grid along y are the mapped interior rows (periodic,
 // transmissive) or the padding rows of a linked face, which hold the
@@ -376,17 +383,28 @@ __global__ void __launch_bounds__(256) k_sweep_yz(SweepParams p, const DevGrid* 
 template <typename T> constexpr int xy_unroll() {
   return sizeof(T) == 4 ? RFV_XY_UNROLL_F32 : RFV_XY_UNROLL_F64;
 }
+// Waves per SIMD the wave-strip form is compiled for (caps its registers).
+#ifndef RFV_XY_WAVE_OCC_F32
+#define RFV_XY_WAVE_OCC_F32 1
+#endif
+#ifndef RFV_XY_WAVE_OCC_F64
+#define RFV_XY_WAVE_OCC_F64 3
+#endif
+template <typename T> constexpr int xy_wave_occupancy() {
+  return sizeof(T) == 4 ? RFV_XY_WAVE_OCC_F32 : RFV_XY_WAVE_OCC_F64;
+}
 
-// CHUNKED: the launch holds a grid whose rows are cut into chunks (the
-// variant without it keeps the decoding of whole rows out of the loop).
-template <typename T, int LAY, bool CHUNKED>
-__global__ void __launch_bounds__(XY_THREADS) k_sweep_xy(SweepParams p,
-                                                         const DevGrid* __restrict__ grids,
-                                                         const int64_t* __restrict__ tile_start,
-                                                         const double* __restrict__ lamv) {
-  constexpr int NT = XY_THREADS;
+// XM: form of the x exchange (XM_ROWS, XM_WAVES); the forms differ only in
+// which lanes hold which cells and how neighbours are read.
+template <typename T, int LAY, int XM>
+__global__ void __launch_bounds__(XM == XM_WAVES ? XY_WAVE_THREADS : XY_THREADS)
+    __attribute__((amdgpu_waves_per_eu(XM == XM_WAVES ? xy_wave_occupancy<T>() : 1)))
+    k_sweep_xy(SweepParams p, const DevGrid* __restrict__ grids,
+               const int64_t* __restrict__ tile_start, const double* __restrict__ lamv) {
+  constexpr bool WAVES = XM == XM_WAVES;
+  constexpr int NT = WAVES ? XY_WAVE_THREADS : XY_THREADS;
   // LDS slots per component: R rows of n0 + 4 slots, R <= NT / XY_MIN_NX
-  constexpr int LN = NT + 4 * (NT / XY_MIN_NX);
+  constexpr int LN = WAVES ? 1 : NT + 4 * (NT / XY_MIN_NX);
   __shared__ T sU[5][LN];
   __shared__ T sR[5][LN];
   __shared__ T sF[5][LN];
@@ -398,40 +416,45 @@ __global__ void __launch_bounds__(XY_THREADS) k_sweep_xy(SweepParams p,
     const int lt = (int)(gt - tile_start[g]);
     const int nx = G.n[0], ny = G.n[1], nz = G.n[2];
     const bool linked_x = G.mode[0] == FACE_HALO || G.mode[1] == FACE_HALO;
-    const int cw = CHUNKED ? xy_chunk_cells(nx, nz, linked_x, NT) : nx;  // cells per x chunk
-    const bool wide = cw < nx;                     // rows cut into chunks
-    const bool ghost_lanes = wide || linked_x;
-    const int nxc = CHUNKED ? (nx + cw - 1) / cw : 1;  // x chunks per row
     const int nseg = (ny + p.seg - 1) / p.seg;
     const int s = lt % nseg;
     const int rest = lt / nseg;
-    const int xch = rest % nxc;
-    const int chunk = rest / nxc;                  // chunk of R rows along z
-    const int xoff = xch * cw;                     // x of the chunk's first cell
-    const int ncx = min(nx - xoff, cw);            // cells of the chunk
-    const int P = ghost_lanes ? ncx + 4 : ncx;     // lanes per row
-    const int R = NT / (ghost_lanes ? cw + 4 : cw);  // rows per tile
-    const int rs = tid / P;                        // row slot of this lane
-    // the lane's x relative to the chunk (-2 .. ncx+1 with ghost lanes)
-    const int xl_ = tid - rs * P - (ghost_lanes ? 2 : 0);
+    // XM_WAVES: wave wv takes entry rest * R + wv of the (z, strip) pairs in
+    // row-major order; XM_ROWS: the tile's R rows lie at consecutive z from
+    // rest * R.
+    const bool ghost_lanes = WAVES || linked_x;
+    const int R = WAVES ? NT / 64 : NT / (ghost_lanes ? nx + 4 : nx);  // rows per tile
+    const int nsx = WAVES ? (nx + XY_WAVE_CELLS - 1) / XY_WAVE_CELLS : 1;  // strips per row
+    const int wv = WAVES ? uniform(tid >> 6) : 0;
+    const int fw = rest * R + wv;
+    const int xoff = WAVES ? (fw % nsx) * XY_WAVE_CELLS : 0;  // x of the strip's first cell
+    const int ncx = WAVES ? min(nx - xoff, XY_WAVE_CELLS) : nx;  // cells of the row or strip
+    const int P = WAVES ? 64 : (ghost_lanes ? nx + 4 : nx);  // lanes per row
+    const int rs = WAVES ? wv : tid / P;           // row slot of this lane
+    // the lane's x relative to xoff (-2 .. ncx+1 with ghost lanes; in a wave
+    // the lanes past ncx+1 hold no cell and only feed discarded values)
+    const int xl_ = WAVES ? (int)__lane_id() - 2 : tid - rs * P - (ghost_lanes ? 2 : 0);
     const int x = xoff + xl_;                      // ... and in the row
-    const int kk = chunk * R + rs;
-    const bool row_on = rs < R && kk < nz;         // the lane belongs to a row
-    const bool on = row_on && xl_ >= 0 && xl_ < ncx;  // ... and holds a cell of the chunk
+    const int kk = WAVES ? fw / nsx : rest * R + rs;
+    const bool row_on = (WAVES || rs < R) && kk < nz;  // the lane belongs to a row
+    if (WAVES && !row_on) continue;                // (uniform over the wave)
+    const bool on = row_on && xl_ >= 0 && xl_ < ncx;  // ... and holds a cell
     // both x faces periodic: the ghost reconstruction and the last face are
     // those of the partner cells (any other case computes them)
     const bool periodic_x =
         !ghost_lanes && G.mode[0] == FACE_PERIODIC && G.mode[1] == FACE_PERIODIC;
-    const int LP = ncx + 4;                        // LDS row pitch
-    const int lb = (row_on ? rs : 0) * LP + 2;     // LDS slot of the chunk's cell 0 in the lane's row
+    const int LP = nx + 4;                         // LDS row pitch
+    const int lb = (row_on ? rs : 0) * LP + 2;     // LDS slot of cell 0 of the lane's row
     const int xl = row_on ? xl_ : 0;               // LDS slot the lane writes: lb + xl
     const int xr = on ? xl_ : 0;                   // slot whose neighbours it reads
     // addresses: column (x, kk) at row j is q0 + (j + 2) Px + lane offset; a
     // ghost lane reads the cell its face names (clamped, wrapped or padding)
-    const int kc = row_on ? kk : chunk * R;
-    const int xc = row_on ? face_index(x, nx, G.mode[0], G.mode[1]) : 0;
+    const int kb = WAVES ? kk : rest * R;          // first z of the tile's rows
+    const int kc = row_on ? kk : kb;
+    const int xq = WAVES ? min(x, nx + 1) : x;
+    const int xc = row_on ? face_index(xq, nx, G.mode[0], G.mode[1]) : 0;
     const int64_t qlane = (int64_t)(kc + 2) * G.pxy + (xc + G.ox);
-    const int64_t q0 = uniform(((int64_t)(chunk * R + 2) * G.pxy + G.ox) & ~int64_t(63));
+    const int64_t q0 = uniform(((int64_t)(kb + 2) * G.pxy + G.ox) & ~int64_t(63));
     const uint32_t lane = Layout<LAY>::rel((uint32_t)(qlane - q0)) * (uint32_t)sizeof(T);
     const uint32_t lane_st =
         Layout<LAY>::rel((uint32_t)(qlane - q0 + (x - xc))) * (uint32_t)sizeof(T);
@@ -453,6 +476,31 @@ __global__ void __launch_bounds__(XY_THREADS) k_sweep_xy(SweepParams p,
 
     // x sweep of one row held by the lanes: u (this lane's cell) -> o
     auto xsweep = [&](const T u[5], T o[5]) __attribute__((always_inline)) {
+      if constexpr (WAVES) {
+        // the same operations as below, with neighbours read by lane shifts
+        T bl[5], br[5];
+        {
+          T dm[5], dp[5];
+#pragma unroll
+          for (int c = 0; c < 5; ++c) {
+            dm[c] = u[c] - from_below(u[c]);
+            dp[c] = from_above(u[c]) - u[c];
+          }
+          hancock<T, 0>(u, dm, dp, hlx, bl, br);
+        }
+        T fl[5];
+        {
+          T left[5];
+#pragma unroll
+          for (int c = 0; c < 5; ++c) left[c] = from_below(br[c]);
+          hllc<T, 0>(left, bl, fl);                      // face x - 1/2
+        }
+        T fp[5];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) fp[c] = from_above(fl[c]);
+        update(u, lamx, fp, fl, o);
+        return;
+      }
       if (row_on && (on || ghost_lanes)) {
 #pragma unroll
         for (int c = 0; c < 5; ++c) sU[c][lb + xl] = u[c];
@@ -611,7 +659,7 @@ __global__ void __launch_bounds__(XY_THREADS) k_sweep_xy(SweepParams p,
         if (on) store_cell_rel<T, LAY>(dst, q0 + (int64_t)(j + 2) * G.px, ptot, lane_st, out);
       }
     }
-    __syncthreads();
+    if constexpr (!WAVES) __syncthreads();
   }
 }
 
@@ -919,24 +967,46 @@ int64_t tiles_yz(const ripple_fv_grid& g, int axis, int yz_block, int yz_segment
   return nchunk * nseg;
 }
 
-// Tiles of the fused sweep (must match the kernel's decoding): rows, or
-// chunks of longer rows (xy_chunk_cells), of R at consecutive z per tile.
+// Tiles of the fused sweep (must match the kernel's decoding).
 bool xy_eligible(const ripple_fv_grid& g) { return g.n[0] >= XY_MIN_NX; }
 
-bool xy_chunked(const ripple_fv_grid& g) {
-  const bool linked = g.nbr[0] >= 0 || g.nbr[1] >= 0;
-  return xy_chunk_cells(g.n[0], g.n[2], linked, XY_THREADS) < g.n[0];
+// Lanes per row of the rows form (0: the row does not fit a workgroup).
+static int xy_row_lanes(const ripple_fv_grid& g) {
+  const int P = (g.nbr[0] >= 0 || g.nbr[1] >= 0) ? g.n[0] + 4 : g.n[0];
+  return P <= XY_THREADS ? P : 0;
 }
 
-int64_t tiles_xy(const ripple_fv_grid& g, int yz_segment) {
-  const bool linked = g.nbr[0] >= 0 || g.nbr[1] >= 0;
-  const int cw = xy_chunk_cells(g.n[0], g.n[2], linked, XY_THREADS);
-  const bool ghost = linked || cw < g.n[0];
-  const int64_t rows = XY_THREADS / (ghost ? cw + 4 : cw);
-  const int64_t nxc = (g.n[0] + cw - 1) / cw;
-  const int64_t nchunk = (g.n[2] + rows - 1) / rows;
+// Cost of a wave-strip lane-row relative to a lane-row of the rows form,
+// measured at 512^3 (1.456 ms against 1.350 ms for FP32 at 512 / 576 of the
+// strip lanes holding cells, 2.89 against 3.37 ms for FP64).
+static double xy_wave_cost(int dtype) { return dtype == RIPPLE_FV_F64 ? 0.76 : 0.96; }
+
+int xy_mode(int dtype, const ripple_fv_grid* grids, int n, int split_xy) {
+  if (split_xy == 3) return XM_WAVES;
+  // lanes occupied per cell, summed over the batch, of either form
+  double rows = 0.0, waves = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const ripple_fv_grid& g = grids[i];
+    const double cells = (double)g.n[0] * g.n[1] * g.n[2];
+    const int P = xy_row_lanes(g);
+    if (P == 0) return XM_WAVES;
+    const int R = XY_THREADS / P;
+    rows += cells * XY_THREADS / ((double)R * g.n[0]);
+    const int nsx = (g.n[0] + XY_WAVE_CELLS - 1) / XY_WAVE_CELLS;
+    waves += cells * xy_wave_cost(dtype) * (64.0 * nsx) / g.n[0];
+  }
+  return split_xy == 0 && waves < rows ? XM_WAVES : XM_ROWS;
+}
+
+int64_t tiles_xy(const ripple_fv_grid& g, int yz_segment, int xmode) {
   const int64_t nseg = (g.n[1] + yz_segment - 1) / yz_segment;
-  return nchunk * nxc * nseg;
+  if (xmode == XM_WAVES) {
+    const int64_t nsx = (g.n[0] + XY_WAVE_CELLS - 1) / XY_WAVE_CELLS;
+    const int64_t waves = XY_WAVE_THREADS / 64;
+    return (g.n[2] * nsx + waves - 1) / waves * nseg;
+  }
+  const int64_t rows = XY_THREADS / xy_row_lanes(g);
+  return (g.n[2] + rows - 1) / rows * nseg;
 }
 
 int64_t tiles_ws(const ripple_fv_grid& g) {
@@ -1004,11 +1074,11 @@ hipError_t launch_sweep(int dtype, int lay, int axis, const Tiling& tl, const Sw
 
 template <typename T, int LAY>
 static hipError_t sweep_xy_typed(const Tiling&, const SweepParams& p, int blocks, hipStream_t s) {
-  if (p.chunked)
-    hipLaunchKernelGGL((k_sweep_xy<T, LAY, true>), dim3(blocks), dim3(XY_THREADS), 0, s, p,
+  if (p.xmode == XM_WAVES)
+    hipLaunchKernelGGL((k_sweep_xy<T, LAY, XM_WAVES>), dim3(blocks), dim3(XY_WAVE_THREADS), 0, s, p,
                        p.w.grids, p.tiles.tile_start, p.w.lam);
   else
-    hipLaunchKernelGGL((k_sweep_xy<T, LAY, false>), dim3(blocks), dim3(XY_THREADS), 0, s, p,
+    hipLaunchKernelGGL((k_sweep_xy<T, LAY, XM_ROWS>), dim3(blocks), dim3(XY_THREADS), 0, s, p,
                        p.w.grids, p.tiles.tile_start, p.w.lam);
   return hipGetLastError();
 }

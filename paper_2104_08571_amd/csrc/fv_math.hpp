@@ -184,6 +184,33 @@ __device__ __forceinline__ void update(const T u[5], T lam, const T fp[5], const
   for (int c = 0; c < 5; ++c) out[c] = fma_(-lam, fp[c] - fm[c], u[c]);
 }
 
+// Whole-wave lane shifts (DPP wave_shr:1 / wave_shl:1): lane l receives the
+// value of lane l - 1 (from_below) or l + 1 (from_above); the end lanes keep
+// their own value and only ever feed discarded results.
+__device__ __forceinline__ float from_below(float v) {
+  const int i = __builtin_bit_cast(int, v);
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(i, i, 0x138, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float from_above(float v) {
+  const int i = __builtin_bit_cast(int, v);
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(i, i, 0x130, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double shift64(double v, int ctrl_below) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const int lo = (int)(uint32_t)u, hi = (int)(uint32_t)(u >> 32);
+  uint32_t a, b;
+  if (ctrl_below) {
+    a = (uint32_t)__builtin_amdgcn_update_dpp(lo, lo, 0x138, 0xF, 0xF, false);
+    b = (uint32_t)__builtin_amdgcn_update_dpp(hi, hi, 0x138, 0xF, 0xF, false);
+  } else {
+    a = (uint32_t)__builtin_amdgcn_update_dpp(lo, lo, 0x130, 0xF, 0xF, false);
+    b = (uint32_t)__builtin_amdgcn_update_dpp(hi, hi, 0x130, 0xF, 0xF, false);
+  }
+  return __builtin_bit_cast(double, ((uint64_t)b << 32) | a);
+}
+__device__ __forceinline__ double from_below(double v) { return shift64(v, 1); }
+__device__ __forceinline__ double from_above(double v) { return shift64(v, 0); }
+
 // |u_d| + c for d = x, y, z; `bad` when rho <= 0, p <= 0 or a value is not finite.
 template <typename T>
 __device__ __forceinline__ void wavespeeds(const T u[5], T s[3], bool& bad) {

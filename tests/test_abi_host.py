@@ -83,7 +83,7 @@ def test_grid_rows_do_not_overlap():
     dict(dtype=2), dict(layout=3), dict(layout=R.AOSOA, aosoa_w=8), dict(layout=R.SOA, aosoa_w=16),
     dict(bc=(0, 2, 0)), dict(tiling=(64, 0, 0, 0)), dict(tiling=(0, 512, 0, 0)),
     dict(tiling=(0, 0, 2, 0)), dict(tiling=(0, 0, 0, -1)), dict(tiling=(0, 0, 0, 0, 3)),
-    dict(tiling=(0, 0, 0, 0, 0, 2)), dict(tiling=(0, 0, 0, 0, 0, -1)),
+    dict(tiling=(0, 0, 0, 0, 0, 4)), dict(tiling=(0, 0, 0, 0, 0, -1)),
     dict(n=(2000, 2000, 2000)),
 ])
 def test_grid_init_rejects(bad):

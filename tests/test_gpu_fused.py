@@ -1,11 +1,12 @@
 """The fused x-then-y sweep gives bitwise the states of the separate x and y
-sweeps, for every layout, precision, boundary condition and row length, and
-for sub-blocks linked along x and/or y (whose padding, corners included,
-the halo copies fill before the pass); grids it does not accept (rows
-outside 16..512 cells) fall back to the separate sweeps with the same
-results.  Also checks the in-place semantics of the step entry points on
-both paths.  Rows longer than a workgroup run fused in chunks of 508
-cells with ghost lanes, also bitwise equal to the separate sweeps."""
+sweeps, in both of its forms (whole rows per workgroup exchanging through
+LDS, split_xy = 2; strips of 60 cells per wave exchanging by lane shifts,
+split_xy = 3) and in the form the library picks (split_xy = 0), for every
+layout, precision, boundary condition and row length, and for sub-blocks
+linked along x and/or y (whose padding, corners included, the halo copies
+fill before the pass); grids it does not accept (rows under 16 cells) fall
+back to the separate sweeps with the same results.  Also checks the
+in-place semantics of the step entry points on both paths."""
 import numpy as np
 import pytest
 import torch
@@ -17,15 +18,21 @@ from paper_2104_08571_amd import ripple_fv as R
 pytestmark = pytest.mark.gpu
 
 
-def run_pair(shape, dtype, layout, aosoa_w, bc, nsteps, cols=0, seed=31, state=None):
+def assert_forms_equal(shape, dtype, layout, aosoa_w, bc, nsteps, cols=0, seed=31, state=None):
+    """Run the separate sweeps (split_xy = 1), the library's pick (0), the
+    rows form (2) and the wave-strip form (3); all must agree bitwise."""
     W = state if state is not None else ist.smooth_periodic(shape, seed=seed)
-    out = []
-    for split in (0, 1):
+    out = {}
+    for split in (1, 0, 2, 3):
         g = R.make_grid(shape, dtype=dtype, layout=layout, aosoa_w=aosoa_w, bc=bc,
                         tiling=(0, 0, 0, 0, cols, split))
         (U,), (t,) = G.run(g, W, nsteps)
-        out.append((U, t))
-    return out
+        out[split] = (U, t)
+    Us, ts = out[1]
+    for split in (0, 2, 3):
+        U, t = out[split]
+        assert t == ts, (shape, bc, split)
+        assert np.array_equal(U, Us), (shape, bc, split)
 
 
 @pytest.mark.parametrize("dtype", [R.F32, R.F64], ids=["f32", "f64"])
@@ -34,24 +41,22 @@ def run_pair(shape, dtype, layout, aosoa_w, bc, nsteps, cols=0, seed=31, state=N
 @pytest.mark.parametrize("cols", [1, 2])
 def test_fused_equals_split(dtype, layout, w, cols):
     for shape, bc in (((37, 29, 11), (1, 1, 1)), ((16, 24, 9), (0, 0, 1)), ((33, 20, 7), (0, 1, 0))):
-        (Uf, tf), (Us, ts) = run_pair(shape, dtype, layout, w, bc, 3, cols)
-        assert tf == ts, shape
-        assert np.array_equal(Uf, Us), (shape, bc)
+        assert_forms_equal(shape, dtype, layout, w, bc, 3, cols)
 
 
-@pytest.mark.parametrize("nx", [2, 3, 16, 17, 56, 57, 58, 59, 60, 61, 62, 255, 508, 509, 512, 513,
-                                520, 1000, 1016, 1017, 1100])
-def test_fused_row_lengths(nx):
+@pytest.mark.parametrize("dtype", [R.F32, R.F64], ids=["f32", "f64"])
+@pytest.mark.parametrize("nx", [2, 3, 16, 17, 56, 57, 58, 59, 60, 61, 62, 119, 120, 121, 255, 300,
+                                508, 509, 512, 513, 520, 1000, 1016, 1017, 1100])
+def test_fused_row_lengths(dtype, nx):
     """Row lengths from 2 to 1100 cells: below, inside and above what one
-    workgroup holds (fused where n0 >= 16, in chunks of 508 cells above 512,
-    separate sweeps below 16), odd lengths; blast (transmissive) vs periodic
-    faces; several z planes per tile."""
+    workgroup holds and around multiples of the 60-cell strip (fused where
+    n0 >= 16, separate sweeps below 16), odd lengths; blast (transmissive)
+    vs periodic faces; several z planes per tile."""
     shape = (nx, 9, 7)
     for bc in ((1, 1, 1), (0, 0, 0)):
         # the blast needs a few cells across it to stay physical
         state = ist.blast(shape) if bc[0] == 0 and nx >= 16 else None
-        (Uf, tf), (Us, ts) = run_pair(shape, R.F32, R.SOA, 0, bc, 2, 0, state=state)
-        assert tf == ts and np.array_equal(Uf, Us), (nx, bc)
+        assert_forms_equal(shape, dtype, R.SOA, 0, bc, 2, 0, state=state)
 
 
 def test_linked_sub_blocks_match_whole_grid():
@@ -63,7 +68,8 @@ def test_linked_sub_blocks_match_whole_grid():
     W = ist.smooth_periodic(shape, seed=77)
     (ref,), (t_ref,) = G.run(whole, W, 3)
     for parts, split in (((1, 2, 1), 0), ((2, 1, 1), 0), ((2, 2, 1), 0), ((2, 3, 2), 0),
-                         ((2, 2, 1), 1)):
+                         ((2, 2, 1), 1), ((1, 2, 1), 3), ((2, 1, 1), 3), ((2, 3, 2), 3),
+                         ((2, 2, 1), 2)):
         subs = [R.copy_grid(sb, split_xy=split) for sb in R.ripple_fv_partition(whole, parts)]
         states, origins = [], []
         for idx, sb in enumerate(subs):
@@ -83,11 +89,13 @@ def test_linked_sub_blocks_match_whole_grid():
     assert e.value.status == R.E_UNSUPPORTED
 
 
-def test_wide_rows_linked_sub_blocks_match_whole_grid():
-    """Rows cut into chunks, on a whole grid and on sub-blocks whose linked x
-    faces fall inside a chunk or at its edge: bitwise the whole grid."""
+@pytest.mark.parametrize("dtype", [R.F32, R.F64], ids=["f32", "f64"])
+def test_wide_rows_linked_sub_blocks_match_whole_grid(dtype):
+    """Rows longer than a workgroup (wave strips), on a whole grid and on
+    sub-blocks whose linked x faces fall inside a strip or at its edge:
+    bitwise the whole grid."""
     shape = (1100, 20, 6)
-    whole = R.make_grid(shape, dtype=R.F32, layout=R.SOA, bc=(1, 0, 1))
+    whole = R.make_grid(shape, dtype=dtype, layout=R.SOA, bc=(1, 0, 1))
     W = ist.smooth_periodic(shape, seed=88)
     (ref,), (t_ref,) = G.run(whole, W, 3)
     split = R.copy_grid(whole, split_xy=1)

@@ -65,7 +65,7 @@ def test_planar_equals_two_identical_planes(dtype):
     """A planar grid (separate x and y sweeps, no z sweep) and the same state
     on two identical periodic z planes (fused x-y pass and a z sweep that
     changes nothing) give the same bits in every plane, for 1, 2 and 5
-    steps: rows inside one workgroup and rows cut into chunks."""
+    steps: rows inside one workgroup and rows longer than one."""
     for nx, ny in ((48, 40), (1100, 12)):
         W1 = ist.smooth_periodic((nx, ny, 1), seed=33)
         W2 = torch.cat([W1, W1], dim=1)
