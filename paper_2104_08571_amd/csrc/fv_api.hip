@@ -34,10 +34,11 @@ struct Plan {
   bool fused = false;                   // x and y sweeps as one pass
   int seg_xy = 0;                       // rows per tile of the fused pass
   int xmode = XM_ROWS;                  // form of the fused pass
-  bool planar = false;                  // separate sweeps, every grid one cell thick in z
-  // the step returns the state to its first buffer (else the separate sweeps
-  // alternate the two buffers from step to step)
-  bool in_place() const { return fused || planar; }
+  bool planar = false;                  // every grid one cell thick in z: no z sweep
+  bool planar_fused = false;            // ... and the x-y pass (wave strips) is the step
+  // the step returns the state to its first buffer (else the passes alternate
+  // the two buffers from step to step)
+  bool in_place() const { return fused || (planar && !planar_fused); }
   std::vector<int64_t> tiles[5];        // prefix: x, y, z, wave-speed, fused x-y tiles
   std::vector<HaloTask> halo[3];
   int64_t halo_area[3] = {0, 0, 0};
@@ -315,23 +316,27 @@ ripple_fv_status build_plan(ripple_fv_ctx* ctx, int n, const ripple_fv_grid* gri
   P->lay = lay_of(grids[0]);
   P->tl = tiling_of(grids[0]);
   P->grids.assign(grids, grids + n);
-  // Grids one cell thick in z run the x and y sweeps separately and skip
-  // the z sweep (the y sweep reduces the next step's wave speeds).  A fused
-  // pass there would be the whole step and would have to reduce the wave
-  // speeds itself: measured on 6400 x 4000 cells such a pass took twice the
-  // time of the two separate sweeps in FP32 (the reduction raises its
-  // register use past two workgroups per CU) and was no faster in FP64.
+  // Grids one cell thick in z skip the z sweep.  Their x and y sweeps run
+  // as one pass in the wave-strip form (whatever split_xy other than 1 asks
+  // for: the rows form does not reduce wave speeds), which is then the whole
+  // step and reduces the next step's wave speeds; with split_xy = 1 or rows
+  // under XY_MIN_NX cells they run separately and the y sweep reduces them.
   P->planar = true;
   for (int g = 0; g < n; ++g) P->planar = P->planar && grids[g].n[2] == 1;
   P->fused = P->tl.split_xy != 1 && !P->planar;
-  for (int g = 0; g < n; ++g) P->fused = P->fused && xy_eligible(grids[g]);
+  P->planar_fused = P->tl.split_xy != 1 && P->planar;
+  for (int g = 0; g < n; ++g) {
+    P->fused = P->fused && xy_eligible(grids[g]);
+    P->planar_fused = P->planar_fused && xy_eligible(grids[g]);
+  }
   // The fused pass marches tiles of seg_xy rows along y.  Where that leaves
   // fewer than XY_MIN_TILES tiles (thin or two-dimensional grids) the
   // segments shrink, down to 16 rows (or the configured segment if that is
   // shorter), so that the launch fills the device.
   P->seg_xy = P->tl.yz_segment;
   if (P->fused) P->xmode = xy_mode(P->dtype, grids, n, P->tl.split_xy);
-  if (P->fused) {
+  if (P->planar_fused) P->xmode = XM_WAVES;
+  if (P->fused || P->planar_fused) {
     int64_t tiles = 0;
     for (int g = 0; g < n; ++g) tiles += tiles_xy(grids[g], P->seg_xy, P->xmode);
     if (tiles < XY_MIN_TILES)
@@ -340,7 +345,7 @@ ripple_fv_status build_plan(ripple_fv_ctx* ctx, int n, const ripple_fv_grid* gri
   }
   for (int k = 0; k < 5; ++k) P->tiles[k].assign(n + 1, 0);
   for (int g = 0; g < n; ++g) {
-    P->tiles[4][g + 1] = P->tiles[4][g] + (P->fused ? tiles_xy(grids[g], P->seg_xy, P->xmode) : 0);
+    P->tiles[4][g + 1] = P->tiles[4][g] + (P->fused || P->planar_fused ? tiles_xy(grids[g], P->seg_xy, P->xmode) : 0);
     P->tiles[0][g + 1] = P->tiles[0][g] + tiles_x(grids[g], P->tl.x_block);
     P->tiles[1][g + 1] = P->tiles[1][g] + tiles_yz(grids[g], 1, P->tl.yz_block, P->tl.yz_segment,
                                                    P->tl.yz_cols);
@@ -545,13 +550,13 @@ ripple_fv_status enqueue_sweep(ripple_fv_ctx* ctx, Plan* P, Launcher& L, int axi
 
 // Enqueue the fused x-then-y sweep (plans whose grids all allow it).
 ripple_fv_status enqueue_sweep_xy(ripple_fv_ctx* ctx, Plan* P, Launcher& L, int in, int out,
-                                  bool per_grid) {
+                                  int fuse_s, bool per_grid) {
   SweepParams sp{};
   sp.w = P->work(ctx->flag);
   sp.in = in;
   sp.out = out;
   sp.seg = P->seg_xy;
-  sp.fuse_s = 0;
+  sp.fuse_s = fuse_s;
   sp.xmode = P->xmode;
   sp.tiles.tile_start = P->d_tiles[4];
   hipEvent_t e1 = nullptr;
@@ -632,9 +637,17 @@ ripple_fv_status enqueue_step(ripple_fv_ctx* ctx, Plan* P, Launcher& L, int cur,
     // neighbour rows first, then the x copy covers them too (corner cells)
     if (!st) st = enqueue_halo(ctx, P, L, 1, cur);
     if (!st) st = enqueue_halo(ctx, P, L, 0, cur, HALO);
-    if (!st) st = enqueue_sweep_xy(ctx, P, L, cur, oth, per_grid);
+    if (!st) st = enqueue_sweep_xy(ctx, P, L, cur, oth, 0, per_grid);
     if (!st) st = enqueue_halo(ctx, P, L, 2, oth);
     if (!st) st = enqueue_sweep(ctx, P, L, 2, oth, cur, 1, per_grid);
+    return st;
+  }
+  if (P->planar_fused) {
+    // a sweep along a one-cell axis changes nothing (see below): the x-y
+    // pass is the whole step and reduces the next step's wave speeds
+    if (!st) st = enqueue_halo(ctx, P, L, 1, cur);
+    if (!st) st = enqueue_halo(ctx, P, L, 0, cur, HALO);
+    if (!st) st = enqueue_sweep_xy(ctx, P, L, cur, oth, 1, per_grid);
     return st;
   }
   if (!st) st = enqueue_halo(ctx, P, L, 0, cur);
@@ -931,7 +944,7 @@ ripple_fv_status ripple_fv_sweep(ripple_fv_ctx* ctx, const ripple_fv_grid* g, in
       return fail(ctx, RIPPLE_FV_E_UNSUPPORTED,
                   "fused x-y sweep needs n[0] >= 16, n[2] >= 2, unlinked x and y faces and "
                   "split_xy != 1");
-    return enqueue_sweep_xy(ctx, P, L, 0, 1, false);
+    return enqueue_sweep_xy(ctx, P, L, 0, 1, 0, false);
   }
   return enqueue_sweep(ctx, P, L, axis, 0, 1, 0, false);
 }

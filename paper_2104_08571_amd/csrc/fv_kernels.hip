@@ -383,7 +383,9 @@ __global__ void __launch_bounds__(256) k_sweep_yz(SweepParams p, const DevGrid* 
 template <typename T> constexpr int xy_unroll() {
   return sizeof(T) == 4 ? RFV_XY_UNROLL_F32 : RFV_XY_UNROLL_F64;
 }
-// Waves per SIMD the wave-strip form is compiled for (caps its registers).
+// Waves per SIMD the wave-strip form is compiled for (caps its registers;
+// the variant that also reduces wave speeds takes what it needs, as a cap of
+// 3 FP64 waves would spill).
 #ifndef RFV_XY_WAVE_OCC_F32
 #define RFV_XY_WAVE_OCC_F32 1
 #endif
@@ -395,13 +397,17 @@ template <typename T> constexpr int xy_wave_occupancy() {
 }
 
 // XM: form of the x exchange (XM_ROWS, XM_WAVES); the forms differ only in
-// which lanes hold which cells and how neighbours are read.
-template <typename T, int LAY, int XM>
+// which lanes hold which cells and how neighbours are read.  FUSE (wave
+// strips only): also reduce |u_d| + c of the new states into the group's
+// wave-speed slots, for grids one cell thick in z, where this pass is the
+// whole step.
+template <typename T, int LAY, int XM, bool FUSE>
 __global__ void __launch_bounds__(XM == XM_WAVES ? XY_WAVE_THREADS : XY_THREADS)
-    __attribute__((amdgpu_waves_per_eu(XM == XM_WAVES ? xy_wave_occupancy<T>() : 1)))
+    __attribute__((amdgpu_waves_per_eu(XM == XM_WAVES && !FUSE ? xy_wave_occupancy<T>() : 1)))
     k_sweep_xy(SweepParams p, const DevGrid* __restrict__ grids,
                const int64_t* __restrict__ tile_start, const double* __restrict__ lamv) {
   constexpr bool WAVES = XM == XM_WAVES;
+  static_assert(WAVES || !FUSE, "the rows form does not reduce wave speeds");
   constexpr int NT = WAVES ? XY_WAVE_THREADS : XY_THREADS;
   // LDS slots per component: R rows of n0 + 4 slots, R <= NT / XY_MIN_NX
   constexpr int LN = WAVES ? 1 : NT + 4 * (NT / XY_MIN_NX);
@@ -600,6 +606,8 @@ __global__ void __launch_bounds__(XM == XM_WAVES ? XY_WAVE_THREADS : XY_THREADS)
     T raw[3][5];
     T xs[3][5];
     T dprev[5], dnext[5], bl[5], br[5], brp[5], fprev[5];
+    T smax[3] = {T(0), T(0), T(0)};
+    bool bad = false;
 #pragma unroll
     for (int k = 0; k < 3; ++k) load_cell_rel<T, LAY>(src, row(j0 - 2 + k), ptot, lane, raw[k]);
 #pragma unroll
@@ -657,6 +665,27 @@ __global__ void __launch_bounds__(XM == XM_WAVES ? XY_WAVE_THREADS : XY_THREADS)
           dprev[c] = dnext[c];
         }
         if (on) store_cell_rel<T, LAY>(dst, q0 + (int64_t)(j + 2) * G.px, ptot, lane_st, out);
+        if constexpr (FUSE) {
+          T sc[3];
+          bool b_ = false;
+          wavespeeds(out, sc, b_);
+          if (on) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) smax[d] = bits_max(smax[d], sc[d]);
+            bad |= b_;
+          }
+        }
+      }
+    }
+    if constexpr (FUSE) {
+      // per wave: no barrier, the waves of a workgroup are independent
+      if (bad) *p.w.flag = 1u;
+      unsigned long long* slot = p.w.s_acc + 3 * G.group;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const unsigned long long bits = __double_as_longlong((double)wave_max(smax[d]));
+        if (__lane_id() == 0 && bits > __atomic_load_n(&slot[d], __ATOMIC_RELAXED))
+          atomicMax(&slot[d], bits);
       }
     }
     if constexpr (!WAVES) __syncthreads();
@@ -1074,12 +1103,15 @@ hipError_t launch_sweep(int dtype, int lay, int axis, const Tiling& tl, const Sw
 
 template <typename T, int LAY>
 static hipError_t sweep_xy_typed(const Tiling&, const SweepParams& p, int blocks, hipStream_t s) {
-  if (p.xmode == XM_WAVES)
-    hipLaunchKernelGGL((k_sweep_xy<T, LAY, XM_WAVES>), dim3(blocks), dim3(XY_WAVE_THREADS), 0, s, p,
-                       p.w.grids, p.tiles.tile_start, p.w.lam);
+  if (p.xmode == XM_WAVES && p.fuse_s)
+    hipLaunchKernelGGL((k_sweep_xy<T, LAY, XM_WAVES, true>), dim3(blocks), dim3(XY_WAVE_THREADS), 0,
+                       s, p, p.w.grids, p.tiles.tile_start, p.w.lam);
+  else if (p.xmode == XM_WAVES)
+    hipLaunchKernelGGL((k_sweep_xy<T, LAY, XM_WAVES, false>), dim3(blocks), dim3(XY_WAVE_THREADS), 0,
+                       s, p, p.w.grids, p.tiles.tile_start, p.w.lam);
   else
-    hipLaunchKernelGGL((k_sweep_xy<T, LAY, XM_ROWS>), dim3(blocks), dim3(XY_THREADS), 0, s, p,
-                       p.w.grids, p.tiles.tile_start, p.w.lam);
+    hipLaunchKernelGGL((k_sweep_xy<T, LAY, XM_ROWS, false>), dim3(blocks), dim3(XY_THREADS), 0, s,
+                       p, p.w.grids, p.tiles.tile_start, p.w.lam);
   return hipGetLastError();
 }
 

@@ -6,10 +6,12 @@ and 9600 x 6000 cells).
 A sweep along a one-cell axis reads the same state on both faces of every
 cell and changes nothing, so a grid with n[2] = 1 is a 2D problem; with
 dx[2] large the z wave speed never sets dt, which then equals the 2D
-solver's dt = CFL min(dx / S_x, dy / S_y).  The library runs the x and y
-sweeps separately on such grids and skips the z sweep: the y sweep reduces
-the next step's wave speeds.  Parity is against the FP64 oracle, which runs
-the full three-sweep step.
+solver's dt = CFL min(dx / S_x, dy / S_y).  The library skips the z sweep
+on such grids and runs the x and y sweeps as one pass (wave strips) that
+also reduces the next step's wave speeds, so the buffers alternate from
+step to step; with split_xy = 1 the sweeps run separately and the y sweep
+reduces the wave speeds.  Parity is against the FP64 oracle, which runs the
+full three-sweep step.
 """
 import numpy as np
 import pytest
@@ -62,28 +64,31 @@ def test_one_cell_axes_match_oracle(oracle, dtype, shape, bc, split):
 
 @pytest.mark.parametrize("dtype", [R.F32, R.F64], ids=["f32", "f64"])
 def test_planar_equals_two_identical_planes(dtype):
-    """A planar grid (separate x and y sweeps, no z sweep) and the same state
-    on two identical periodic z planes (fused x-y pass and a z sweep that
-    changes nothing) give the same bits in every plane, for 1, 2 and 5
-    steps: rows inside one workgroup and rows longer than one."""
+    """A planar grid (one x-y pass per step, no z sweep, or separate x and y
+    sweeps) and the same state on two identical periodic z planes (x-y pass
+    and a z sweep that changes nothing) give the same bits in every plane,
+    for 1, 2 and 5 steps: rows inside one workgroup and rows longer than
+    one."""
     for nx, ny in ((48, 40), (1100, 12)):
         W1 = ist.smooth_periodic((nx, ny, 1), seed=33)
         W2 = torch.cat([W1, W1], dim=1)
-        g1 = R.make_grid((nx, ny, 1), dtype=dtype, layout=R.SOA, bc=(1, 0, 1),
-                         dx=(1.0 / nx, 1.0 / ny, 1.0))
         g2 = R.make_grid((nx, ny, 2), dtype=dtype, layout=R.SOA, bc=(1, 0, 1),
                          dx=(1.0 / nx, 1.0 / ny, 1.0))
-        for n in (1, 2, 5):
-            (a,), ta = G.run(g1, W1, n)
-            (b,), tb = G.run(g2, W2, n, flags=R.RUN_GRAPH)
-            assert ta == tb, (nx, n)
-            assert np.array_equal(b[:, :1], a) and np.array_equal(b[:, 1:], a), (nx, n)
+        for split in (0, 1):
+            g1 = R.make_grid((nx, ny, 1), dtype=dtype, layout=R.SOA, bc=(1, 0, 1),
+                             dx=(1.0 / nx, 1.0 / ny, 1.0), tiling=(0, 0, 0, 0, 0, split))
+            for n in (1, 2, 5):
+                (a,), ta = G.run(g1, W1, n)
+                (b,), tb = G.run(g2, W2, n, flags=R.RUN_GRAPH)
+                assert ta == tb, (nx, split, n)
+                assert np.array_equal(b[:, :1], a) and np.array_equal(b[:, 1:], a), (nx, split, n)
 
 
 @pytest.mark.parametrize("split", [0, 1])
 def test_planar_graph_step_counts(split):
-    """Graph replays equal the eager loop for odd and even step counts, with
-    and without split_xy set (planar grids run separate sweeps either way)."""
+    """Graph replays equal the eager loop for odd and even step counts (the
+    one-pass planar step alternates buffers and copies back after odd
+    counts; the separate sweeps return the state in place)."""
     shape = (600, 40, 1)   # rows longer than one workgroup
     W = ist.smooth_periodic(shape, seed=34)
     g = R.make_grid(shape, dtype=R.F32, layout=R.SOA, bc=(1, 1, 1),
