@@ -120,16 +120,18 @@ enum ripple_fv_kernel_kind {
  *           yz_cols: adjacent x cells per thread of the separate y and z
  *           sweeps (1, 2; 0 = 2 for FP32 SoA/AoSoA, else 1); FP64 always
  *           runs 1 (2 is accepted and means 1); the fused x-y sweep always
- *           runs one cell per thread in workgroups of 512;
+ *           runs one cell per thread;
  *           split_xy: how the x and y sweeps run.  0 = as one fused pass
- *           wherever every grid of the batch allows it (n[0] >= 16, and not
- *           every grid one cell thick in z), in the form that occupies fewer
- *           vector lanes per cell by a measured cost model: whole rows per
- *           workgroup with neighbours exchanged through LDS, or strips of 60
- *           cells per wave with neighbours exchanged by lane shifts (any row
- *           length); 1 = always as two separate sweeps; 2 = fused, whole
- *           rows where every row fits a workgroup of 512 lanes (n[0] <= 512,
- *           508 with a linked x face), else strips; 3 = fused, strips
+ *           wherever every grid of the batch allows it (n[0] >= 16), in the
+ *           form that occupies fewer vector lanes per cell by a measured
+ *           cost model: whole rows per workgroup of 512 lanes with
+ *           neighbours exchanged through LDS, or strips of 60 cells per wave
+ *           with neighbours exchanged by lane shifts (any row length);
+ *           1 = always as two separate sweeps; 2 = fused, whole rows where
+ *           every row fits a workgroup (n[0] <= 512, 508 with a linked x
+ *           face), else strips; 3 = fused, strips.  When every grid is one
+ *           cell thick in z, any value but 1 runs the strips form, which
+ *           then also reduces the wave speeds
  *  reserved must be 0
  *  x_origin OUT: padded x index of interior cell x = 0 (see below)
  *  pitch, bytes   OUT: padded extents (Px, Py, Pz) and bytes of one buffer
@@ -229,8 +231,8 @@ ripple_fv_status ripple_fv_sweep(ripple_fv_ctx* ctx, const ripple_fv_grid* g, in
  * state before and after; work is a second buffer of g->bytes that the step
  * clobbers (where the x and y sweeps run as one fused pass the step is
  * u -> work -> u; otherwise the three sweeps ping-pong and the result is
- * copied back; one cell thick in z: u -> work -> u by the x and y sweeps
- * alone).  cfl in (0, 1].  dt_dev: optional device double receiving
+ * copied back; one cell thick in z: u -> work by the one x-y pass and a
+ * copy back, or u -> work -> u by separate x and y sweeps).  cfl in (0, 1].  dt_dev: optional device double receiving
  * the dt used. */
 ripple_fv_status ripple_fv_step(ripple_fv_ctx* ctx, const ripple_fv_grid* g, void* u,
                                 void* work, double cfl, double dt, double* dt_dev,
@@ -250,10 +252,11 @@ ripple_fv_status ripple_fv_step(ripple_fv_ctx* ctx, const ripple_fv_grid* g, voi
  * flags: ripple_fv_run_flags.  The first call for a given set of grid
  * descriptors builds and caches a plan (workspaces, tile lists, graphs);
  * later calls with the same descriptors allocate nothing.  When every grid
- * is one cell thick in z, a step is x (u -> work) and y (work -> u) only:
- * the z sweep would change nothing, and the y sweep reduces the next step's
- * wave speeds instead (such grids always run the x and y sweeps
- * separately). */
+ * is one cell thick in z the z sweep, which would change nothing, is
+ * skipped: a step is one x-y pass (u -> work, roles swapped every step, one
+ * copy back after an odd number of steps) that also reduces the next step's
+ * wave speeds, or with split_xy = 1 (or n[0] < 16) x (u -> work) and y
+ * (work -> u), the y sweep reducing the wave speeds. */
 ripple_fv_status ripple_fv_run_batch(ripple_fv_ctx* ctx, int32_t n, const ripple_fv_grid* grids,
                                      void* const* u, void* const* work, int32_t nsteps,
                                      double cfl, int32_t flags, void* stream);
