@@ -365,8 +365,9 @@ __global__ void __launch_bounds__(256) k_sweep_yz(SweepParams p, const DevGrid* 
 // neighbour's: the x halo copy that precedes this pass covers the y padding
 // rows); the pass x-sweeps them like any other row.
 //
-// Rings (period 3): raw rows are loaded three iterations before they are
-// x-swept; x-swept rows j, j+1, j+2 are held while cell j is updated.
+// Rings: raw rows are loaded PF iterations before they are x-swept (PF = 3
+// in the rows form, 1 in the wave strips); x-swept rows j, j+1, j+2 are
+// held while cell j is updated (period 3).
 //
 // Iterations per trip of the marching loop, a multiple of the ring period 3.
 // Loads issued in an earlier trip are waited for at a trip's first use (the
@@ -394,6 +395,25 @@ template <typename T> constexpr int xy_unroll() {
 #endif
 template <typename T> constexpr int xy_wave_occupancy() {
   return sizeof(T) == 4 ? RFV_XY_WAVE_OCC_F32 : RFV_XY_WAVE_OCC_F64;
+}
+// Rows loaded ahead of their x sweep (1, 2 or 3).  The wave strips load one
+// row ahead: that frees 10 registers per lane in FP32 (80: six waves per
+// SIMD) and 20 in FP64 (150; 163 with the wave-speed reduction, three waves
+// instead of two), and measured faster: the one-pass planar step at
+// 6400 x 4000 took 0.317 ms against 0.364 with three rows ahead in FP32,
+// 0.539 against 0.569 in FP64; the 1024^3 FP32 step 21.8 ms against 22.5.
+#ifndef RFV_XY_PF_ROWS
+#define RFV_XY_PF_ROWS 3
+#endif
+#ifndef RFV_XY_PF_WAVES_F32
+#define RFV_XY_PF_WAVES_F32 1
+#endif
+#ifndef RFV_XY_PF_WAVES_F64
+#define RFV_XY_PF_WAVES_F64 1
+#endif
+template <typename T, int XM> constexpr int xy_prefetch() {
+  return XM != XM_WAVES ? RFV_XY_PF_ROWS
+                        : (sizeof(T) == 4 ? RFV_XY_PF_WAVES_F32 : RFV_XY_PF_WAVES_F64);
 }
 
 // XM: form of the x exchange (XM_ROWS, XM_WAVES); the forms differ only in
@@ -602,29 +622,31 @@ __global__ void __launch_bounds__(XM == XM_WAVES ? XY_WAVE_THREADS : XY_THREADS)
       update(u, lamx, fp, fl, o);
     };
 
-    // raw ring slot of row r and x-swept ring slot: (r - (j0 - 2)) mod 3
-    T raw[3][5];
+    // raw ring slot of row r: (r - (j0 - 2)) mod PF (rows are loaded PF rows
+    // before they are x-swept); x-swept ring slot: (r - (j0 - 2)) mod 3
+    constexpr int PF = xy_prefetch<T, XM>();
+    T raw[PF][5];
     T xs[3][5];
     T dprev[5], dnext[5], bl[5], br[5], brp[5], fprev[5];
     T smax[3] = {T(0), T(0), T(0)};
     bool bad = false;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) load_cell_rel<T, LAY>(src, row(j0 - 2 + k), ptot, lane, raw[k]);
+    for (int k = 0; k < PF; ++k) load_cell_rel<T, LAY>(src, row(j0 - 2 + k), ptot, lane, raw[k]);
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      xsweep(raw[k], xs[k]);                                      // rows j0-2, j0-1, j0
-      load_cell_rel<T, LAY>(src, row(j0 + 1 + k), ptot, lane, raw[k]);
+    for (int i = 0; i < 4; ++i) {
+      xsweep(raw[i % PF], xs[i % 3]);                               // rows j0-2 .. j0+1
+      load_cell_rel<T, LAY>(src, row(j0 - 2 + i + PF), ptot, lane, raw[i % PF]);
+      if (i == 2) {
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+          dprev[c] = xs[1][c] - xs[0][c];
+          dnext[c] = xs[2][c] - xs[1][c];
+        }
+        hancock<T, 1>(xs[1], dprev, dnext, hly, bl, brp);          // cell j0 - 1
+#pragma unroll
+        for (int c = 0; c < 5; ++c) dprev[c] = dnext[c];
+      }
     }
-#pragma unroll
-    for (int c = 0; c < 5; ++c) {
-      dprev[c] = xs[1][c] - xs[0][c];
-      dnext[c] = xs[2][c] - xs[1][c];
-    }
-    hancock<T, 1>(xs[1], dprev, dnext, hly, bl, brp);              // cell j0 - 1
-#pragma unroll
-    for (int c = 0; c < 5; ++c) dprev[c] = dnext[c];
-    xsweep(raw[0], xs[0]);                                          // row j0 + 1
-    load_cell_rel<T, LAY>(src, row(j0 + 4), ptot, lane, raw[0]);
 #pragma unroll
     for (int c = 0; c < 5; ++c) dnext[c] = xs[0][c] - xs[2][c];
     hancock<T, 1>(xs[2], dprev, dnext, hly, bl, br);                // cell j0
@@ -636,19 +658,20 @@ __global__ void __launch_bounds__(XM == XM_WAVES ? XY_WAVE_THREADS : XY_THREADS)
     }
 
     // Iteration o (cell j = j0 + o), k = o mod U: xs[(k+2)%3] = U_j,
-    // xs[k%3] = U_{j+1}; row j+2 is x-swept from raw[(k+1)%3] into
-    // xs[(k+1)%3] (the slot of U_{j-1}), and row j+5 is loaded into the raw
-    // slot just consumed.  dprev = U_{j+1} - U_j, brp = Ub^R_j, fprev = F_{j-1/2}.
+    // xs[k%3] = U_{j+1}; row j+2 is x-swept from raw[(k+4)%PF] into
+    // xs[(k+1)%3] (the slot of U_{j-1}), and row j+2+PF is loaded into the
+    // raw slot just consumed.  dprev = U_{j+1} - U_j, brp = Ub^R_j,
+    // fprev = F_{j-1/2}.
     constexpr int U = xy_unroll<T>();
-    static_assert(U % 3 == 0, "the loop must advance the rings by whole periods");
+    static_assert(U % 3 == 0 && U % PF == 0, "the loop must advance the rings by whole periods");
     for (int o0 = 0; o0 < len; o0 += U) {
 #pragma unroll
       for (int k = 0; k < U; ++k) {
         const int o = o0 + k;
         if (o >= len) break;
         const int j = j0 + o;
-        xsweep(raw[(k + 1) % 3], xs[(k + 1) % 3]);                 // row j + 2
-        load_cell_rel<T, LAY>(src, row(j + 5), ptot, lane, raw[(k + 1) % 3]);
+        xsweep(raw[(k + 4) % PF], xs[(k + 1) % 3]);                // row j + 2
+        load_cell_rel<T, LAY>(src, row(j + 2 + PF), ptot, lane, raw[(k + 4) % PF]);
         const T* uj = xs[(k + 2) % 3];
         const T* uj1 = xs[k % 3];
         const T* uj2 = xs[(k + 1) % 3];
