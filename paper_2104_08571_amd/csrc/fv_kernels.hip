@@ -329,10 +329,10 @@ __global__ void __launch_bounds__(256) k_sweep_yz(SweepParams p, const DevGrid* 
 
 // The y sweep of cell (i, j, k) reads the x-swept states of column (i, k) at
 // rows j-2 .. j+2 only, and the x sweep of a row needs nothing but that row.
-// So a workgroup that owns whole x rows of a few z planes can march along y,
-// x-sweep each row it loads (neighbours exchanged through LDS) and feed the
-// result straight into the y sweep's register window: the state is read and
-// written once for both sweeps.  Each cell undergoes exactly the arithmetic
+// So lanes that hold a stretch of an x row (with its neighbours) can march
+// along y, x-sweep each row they load and feed the result straight into the
+// y sweep's register window: the state is read and written once for both
+// sweeps.  Each cell undergoes exactly the arithmetic
 // of k_sweep_x followed by k_sweep_yz along y, so the result is bitwise that
 // of the two separate kernels.
 //
@@ -372,9 +372,10 @@ __global__ void __launch_bounds__(256) k_sweep_yz(SweepParams p, const DevGrid* 
 // Iterations per trip of the marching loop, a multiple of the ring period 3.
 // Loads issued in an earlier trip are waited for at a trip's first use (the
 // wait counter is merged conservatively at the loop head), so longer trips
-// keep a little more in flight.  Measured at 512^3, FP32: 3 -> 1.444 ms,
-// 6 -> 1.394, 9 -> 1.387, 12 -> 1.397; FP64: 3.874 / 3.852 / 3.888 / 3.902,
-// and at 15 the FP64 loop outgrows the instruction cache (5.27 ms).
+// keep a little more in flight.  Measured at 512^3 in the rows form, FP32:
+// 3 -> 1.444 ms, 6 -> 1.394, 9 -> 1.387, 12 -> 1.397; FP64: 3.874 / 3.852 /
+// 3.888 / 3.902, and at 15 the FP64 loop outgrows the instruction cache
+// (5.27 ms).
 #ifndef RFV_XY_UNROLL_F32
 #define RFV_XY_UNROLL_F32 9
 #endif
@@ -385,8 +386,8 @@ template <typename T> constexpr int xy_unroll() {
   return sizeof(T) == 4 ? RFV_XY_UNROLL_F32 : RFV_XY_UNROLL_F64;
 }
 // Waves per SIMD the wave-strip form is compiled for (caps its registers;
-// the variant that also reduces wave speeds takes what it needs, as a cap of
-// 3 FP64 waves would spill).
+// the variant that also reduces wave speeds is left uncapped: it needs 163
+// registers in FP64, three waves per SIMD).
 #ifndef RFV_XY_WAVE_OCC_F32
 #define RFV_XY_WAVE_OCC_F32 1
 #endif

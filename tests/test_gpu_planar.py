@@ -49,7 +49,7 @@ def oracle_run(oracle, W, nsteps, dx, bc):
 @pytest.mark.parametrize("shape,bc,split", [
     ((40, 24, 1), (1, 1, 1), 1), ((40, 24, 1), (1, 1, 1), 0), ((37, 29, 1), (0, 1, 0), 1),
     ((1, 30, 20), (0, 1, 1), 1), ((30, 1, 20), (1, 0, 1), 1), ((30, 1, 20), (1, 0, 1), 0),
-    ((1, 1, 9), (0, 0, 1), 1)])
+    ((1, 1, 9), (0, 0, 1), 1), ((12, 20, 1), (1, 0, 1), 0), ((70, 9, 1), (0, 1, 0), 3)])
 def test_one_cell_axes_match_oracle(oracle, dtype, shape, bc, split):
     W = ist.random_physical(shape, 12) if min(shape) == 1 and shape.count(1) > 1 else \
         ist.smooth_periodic(shape, seed=21)
