@@ -105,6 +105,30 @@ def test_smooth_512_fp32(oracle):
     assert (drift < 1e-8).all(), drift
 
 
+def test_smooth_512_fp64(oracle):
+    """512^3 FP64 periodic, the benchmark's FP64 comparison run (the fused
+    pass in its wave-strip form): one step against the oracle on the whole
+    grid; 20 steps keep the totals to FP64 round-off."""
+    n = (512, 512, 512)
+    W = ist.smooth_periodic(n, seed=8571, device="cuda")
+    g = R.make_grid(n, dtype=R.F64, layout=R.SOA, bc=(1, 1, 1))
+    log("512^3 fp64: oracle 1 step")
+    t0 = time.time()
+    ref, t_ref, _ = oracle.run(oracle.prim_to_cons(W.cpu().numpy()), 1, G.unit_dx(n), [1, 1, 1])
+    log(f"oracle done in {time.time() - t0:.1f} s")
+    (gpu,), (t,) = G.run(g, W, 1)
+    err = G.assert_parity(gpu, ref, 1e-12, "512^3 fp64 1 step")
+    assert abs(t - t_ref) <= 1e-14 * t_ref
+    log(f"rel L1 after 1 step {err}")
+    del ref, gpu
+    U0 = G.export(g, G.load(g, W))
+    buf = run_keep([g], [W], 20, flags=R.RUN_GRAPH)[0]
+    s1 = sums(g, buf)
+    drift = np.abs(s1 - U0.reshape(5, -1).sum(1)) / abs_sums(U0)
+    log(f"20-step conservation drift (FP64) {drift}")
+    assert (drift < 1e-13).all(), drift
+
+
 def test_batch_64_grids(oracle):
     """64 grids with extents drawn from {32, 48, ..., 192}: batched graph
     replay == per-grid launches bitwise; three sampled grids match the oracle."""
