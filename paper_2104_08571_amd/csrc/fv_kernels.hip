@@ -1031,12 +1031,14 @@ static int xy_row_lanes(const ripple_fv_grid& g) {
 
 // Cost of a wave-strip lane-row relative to a lane-row of the rows form.
 // FP64, measured at 512^3: 2.89 against 3.37 ms with 576 strip lanes per 512
-// cells.  FP32, measured at 384^3 and 256^3: 0.798 against 0.770 ms (448
-// strip lanes per 384 cells, rows of 384 in 512-lane workgroups) and 0.236
-// against 0.200 ms (320 per 256, two rows per workgroup); the rows form also
-// won at 512^3 (1.35 against 1.54 ms), so in FP32 the strips take rows that
-// do not fit a workgroup or leave most of one idle.
-static double xy_wave_cost(int dtype) { return dtype == RIPPLE_FV_F64 ? 0.76 : 1.18; }
+// cells.  FP32: the rows form won on a 512^3 grid (1.35 against 1.54 ms,
+// both forms using every lane of their workgroups but 11 % of the strip
+// lanes holding no cell) and on a 256^3 grid (0.200 against 0.236 ms, two
+// rows per workgroup), the strips on 2 x 2 x 2 sub-blocks of 384^3 with
+// linked x faces (5.26 against 6.01 ms, rows of 388 lanes in 512-lane
+// workgroups); any value between 0.89 and 1.14 picks the faster form in all
+// three.
+static double xy_wave_cost(int dtype) { return dtype == RIPPLE_FV_F64 ? 0.76 : 1.0; }
 
 int xy_mode(int dtype, const ripple_fv_grid* grids, int n, int split_xy) {
   if (split_xy == 3) return XM_WAVES;
