@@ -185,15 +185,17 @@ __device__ __forceinline__ void update(const T u[5], T lam, const T fp[5], const
 }
 
 // Whole-wave lane shifts (DPP wave_shr:1 / wave_shl:1): lane l receives the
-// value of lane l - 1 (from_below) or l + 1 (from_above); the end lanes keep
-// their own value and only ever feed discarded results.
+// value of lane l - 1 (from_below) or l + 1 (from_above).  In FP32 the end
+// lanes receive zero, which lets the compiler fold a shift into the
+// instruction that consumes it; in FP64 they keep their own value.  Either
+// way the end lanes only ever feed discarded results.
 __device__ __forceinline__ float from_below(float v) {
   const int i = __builtin_bit_cast(int, v);
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(i, i, 0x138, 0xF, 0xF, false));
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(i, 0x138, 0xF, 0xF, true));
 }
 __device__ __forceinline__ float from_above(float v) {
   const int i = __builtin_bit_cast(int, v);
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(i, i, 0x130, 0xF, 0xF, false));
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(i, 0x130, 0xF, 0xF, true));
 }
 __device__ __forceinline__ double shift64(double v, int ctrl_below) {
   const uint64_t u = __builtin_bit_cast(uint64_t, v);
