@@ -493,8 +493,9 @@ def main():
                          "(0 = library default; split_xy 1 = separate x and y sweeps, "
                          "2 / 3 = fused pass in the rows / wave-strip form)")
     ap.add_argument("--no-f64", action="store_true", help="skip the FP64 comparison run")
-    ap.add_argument("--cpu-steps", type=int, default=1,
-                    help="oracle steps timed for cpu_baseline (0 = skip)")
+    ap.add_argument("--cpu-steps", type=int, default=3,
+                    help="oracle steps timed for cpu_baseline (0 = skip); 3 steps of the "
+                         "512^3 workload are about 12 s on 16 host threads")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the batched and partitioned workloads")
     ap.add_argument("--no-force2d", action="store_true",
