@@ -232,14 +232,24 @@ ripple_fv_status ripple_fv_sweep(ripple_fv_ctx* ctx, const ripple_fv_grid* g, in
  * clobbers (where the x and y sweeps run as one fused pass the step is
  * u -> work -> u; otherwise the three sweeps ping-pong and the result is
  * copied back; one cell thick in z: u -> work by the one x-y pass and a
- * copy back, or u -> work -> u by separate x and y sweeps).  cfl in (0, 1].  dt_dev: optional device double receiving
- * the dt used. */
+ * copy back, or u -> work -> u by separate x and y sweeps).  cfl in (0, 1].
+ * dt_dev: optional device double receiving the dt used.
+ *
+ * In place rather than in -> out: the paper's graph swaps an input and an
+ * output tensor after every update (swap_in_out), so a three-update step
+ * leaves its result in the other buffer.  Here the x and y updates run as
+ * one pass over the state, so a step is two passes, u -> work -> u, and the
+ * result is back in u with no copy; an in -> out contract would cost one more
+ * read and write of the whole state per step.  Callers that ping-pong
+ * buffers keep passing the same pair. */
 ripple_fv_status ripple_fv_step(ripple_fv_ctx* ctx, const ripple_fv_grid* g, void* u,
                                 void* work, double cfl, double dt, double* dt_dev,
                                 void* stream);
 
 /* Advance n independent grids (or sub-blocks of partitioned domains) by
- * nsteps steps, in place.  Every grid uses its group's dt from the CFL
+ * nsteps steps, in place: the result is in u[i] for every step count (the
+ * work buffers' roles alternate inside, never the caller's; see
+ * ripple_fv_step for why the state returns to its own buffer).  Every grid uses its group's dt from the CFL
  * condition.  u[i]: the state of grid i, before and after; work[i]: a second
  * buffer of grids[i].bytes, clobbered.  A step runs the x and y sweeps as one
  * fused pass (u -> work) and the z sweep (work -> u) where every grid allows
@@ -299,13 +309,19 @@ ripple_fv_status ripple_fv_halo_exchange(ripple_fv_ctx* ctx, int32_t n,
 ripple_fv_status ripple_fv_conserved_sums(ripple_fv_ctx* ctx, const ripple_fv_grid* g,
                                           const void* u, double* sums_dev, void* stream);
 
-/* Error norms of u against ref (FP64 conserved, planar [5][n2][n1][n0],
- * device), accumulated in FP64: out_dev (device, 20 doubles) receives per
- * variable c the four values sum|u - ref|, sum|ref|, max|u - ref|, max|ref|
- * at out_dev[4 c + 0..3]. */
+/* Relative error norms of u against ref per conserved variable, over the
+ * interior cells, accumulated in FP64 in a fixed order (deterministic):
+ *   l1_dev[c]   = sum |u_c - ref_c| / sum |ref_c|
+ *   linf_dev[c] = max |u_c - ref_c| / max |ref_c|
+ * for c = rho, m_x, m_y, m_z, E (each 5 doubles, device).  A variable whose
+ * reference vanishes everywhere gives 0 where u matches it exactly, else
+ * +inf.  ref_dev: FP64 conserved variables of the same grid, planar
+ * [5][n2][n1][n0] (device).  These are the diagnostic norms the FP32 path's
+ * error against an FP64 reference is stated in; the maxima are exact, so
+ * linf is one correctly rounded division. */
 ripple_fv_status ripple_fv_error_norms(ripple_fv_ctx* ctx, const ripple_fv_grid* g,
-                                       const void* u, const double* ref_dev, double* out_dev,
-                                       void* stream);
+                                       const void* u, const double* ref_dev, double* l1_dev,
+                                       double* linf_dev, void* stream);
 
 /* Wait for the device, then report and clear the sticky non-physical flag:
  * E_NONPHYSICAL if any kernel since the last check met rho <= 0, p <= 0 or

@@ -175,6 +175,23 @@ ripple_fv_status grid_check(const ripple_fv_grid* g, int64_t pitch[3], int64_t* 
   }
   const int64_t b = cells * 5 * elem;
   if (b > MAX_BYTES) { *why = "grid too large"; return RIPPLE_FV_E_INVALID; }
+  // Per-lane byte offsets from a tile's wave-uniform base are 32-bit buffer
+  // offsets.  The tiles that span the most memory are the rows form of the
+  // fused x-y pass (up to XY_THREADS / n0 rows at consecutive z) and the
+  // separate y sweep (lanes across x, then z: up to 2 * 256 / n0 + 1
+  // planes); every other tile stays within a few rows.  Bound the largest
+  // span generously by 2 * XY_THREADS / n0 + 2 planes (at most n2): that
+  // many plane pitches plus a row pitch and the alignment slack, times the
+  // cells' element stride (5 in AoS and AoSoA).
+  {
+    const int64_t planes = std::min<int64_t>(g->n[2], 2 * XY_THREADS / g->n[0] + 2);
+    const int64_t span_cells = (planes - 1) * px * py + px + ox + 64;
+    const int64_t stride = g->layout == RIPPLE_FV_SOA ? 1 : 5;
+    if (span_cells * stride * elem >= (int64_t(1) << 31)) {
+      *why = "grid too large for 32-bit lane offsets (a thin x extent with large y-z planes)";
+      return RIPPLE_FV_E_INVALID;
+    }
+  }
   pitch[0] = px;
   pitch[1] = py;
   pitch[2] = pz;
@@ -1060,17 +1077,18 @@ ripple_fv_status ripple_fv_conserved_sums(ripple_fv_ctx* ctx, const ripple_fv_gr
 }
 
 ripple_fv_status ripple_fv_error_norms(ripple_fv_ctx* ctx, const ripple_fv_grid* g,
-                                       const void* u, const double* ref_dev, double* out_dev,
-                                       void* stream) {
+                                       const void* u, const double* ref_dev, double* l1_dev,
+                                       double* linf_dev, void* stream) {
   ripple_fv_status st = set_device(ctx);
   if (st) return st;
   if ((st = grid_ok(ctx, g))) return st;
   const int64_t ncell = (int64_t)g->n[0] * g->n[1] * g->n[2];
   if ((st = ptr_ok(ctx, u, g->bytes, 256, "u"))) return st;
   if ((st = ptr_ok(ctx, ref_dev, ncell * 40, 8, "ref_dev"))) return st;
-  if ((st = ptr_ok(ctx, out_dev, 160, 8, "out_dev"))) return st;
+  if ((st = ptr_ok(ctx, l1_dev, 40, 8, "l1_dev"))) return st;
+  if ((st = ptr_ok(ctx, linf_dev, 40, 8, "linf_dev"))) return st;
   const int nb = (int)std::min<int64_t>(DIAG_MAX_BLOCKS, (ncell + DIAG_BLOCK - 1) / DIAG_BLOCK);
-  HIP_OR_FAIL(ctx, launch_norms(desc_of(*g, u), ref_dev, ctx->partials, nb, out_dev,
+  HIP_OR_FAIL(ctx, launch_norms(desc_of(*g, u), ref_dev, ctx->partials, nb, l1_dev, linf_dev,
                                 (hipStream_t)stream));
   return RIPPLE_FV_OK;
 }

@@ -133,7 +133,7 @@ hipError_t launch_convert(const Desc& src, const Desc& dst, hipStream_t s);
 hipError_t launch_tune_state(double* W, const int n[3], hipStream_t s);
 hipError_t launch_sums(const Desc& d, double* partials, int nblocks, double* out, hipStream_t s);
 hipError_t launch_norms(const Desc& d, const double* ref, double* partials, int nblocks,
-                        double* out, hipStream_t s);
+                        double* l1, double* linf, hipStream_t s);
 // Context services for entry points outside the step's translation unit:
 // select the context's device and clear its error text; record an error;
 // check that a device pointer is aligned and covers `bytes`.

@@ -980,6 +980,36 @@ __global__ void __launch_bounds__(DIAG_BLOCK) k_finish(const double* partials, i
     for (int k = 0; k < NVAL; ++k) out[k] = acc[k];
 }
 
+// Relative norms per variable from the four totals sum|u - ref|, sum|ref|,
+// max|u - ref|, max|ref| (k_norms layout): l1 = sum|u - ref| / sum|ref| and
+// linf = max|u - ref| / max|ref|; a vanishing reference gives 0 where the
+// error vanishes too, else +inf.
+__device__ __forceinline__ double rel_norm(double err, double ref) {
+  return ref > 0.0 ? err / ref : (err == 0.0 ? 0.0 : __builtin_huge_val());
+}
+
+__global__ void __launch_bounds__(DIAG_BLOCK) k_finish_norms(const double* partials, int nblocks,
+                                                             double* l1, double* linf) {
+  __shared__ double lds[20 * DIAG_BLOCK];
+  int kind[20];
+  for (int k = 0; k < 20; ++k) kind[k] = (k & 3) >= 2;
+  double acc[20];
+  for (int k = 0; k < 20; ++k) acc[k] = 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += DIAG_BLOCK)
+    for (int k = 0; k < 20; ++k) {
+      const double v = partials[b * 20 + k];
+      acc[k] = kind[k] ? __builtin_fmax(acc[k], v) : acc[k] + v;
+    }
+  block_reduce<20>(acc, kind, lds);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      l1[c] = rel_norm(acc[4 * c + 0], acc[4 * c + 1]);
+      linf[c] = rel_norm(acc[4 * c + 2], acc[4 * c + 3]);
+    }
+  }
+}
+
 // Smooth periodic primitive state used by the autotuner to time candidates
 // (rho = 1 + 0.2 sin, small velocities, p = 1), planar FP64 [5][n2][n1][n0].
 __global__ void k_tune_state(double* W, int nx, int ny, int nz) {
@@ -1264,9 +1294,9 @@ hipError_t launch_sums(const Desc& d, double* partials, int nblocks, double* out
 }
 
 hipError_t launch_norms(const Desc& d, const double* ref, double* partials, int nblocks,
-                        double* out, hipStream_t s) {
+                        double* l1, double* linf, hipStream_t s) {
   hipLaunchKernelGGL(k_norms, dim3(nblocks), dim3(DIAG_BLOCK), 0, s, d, ref, partials);
-  hipLaunchKernelGGL((k_finish<20>), dim3(1), dim3(DIAG_BLOCK), 0, s, partials, nblocks, out, 1);
+  hipLaunchKernelGGL(k_finish_norms, dim3(1), dim3(DIAG_BLOCK), 0, s, partials, nblocks, l1, linf);
   return hipGetLastError();
 }
 

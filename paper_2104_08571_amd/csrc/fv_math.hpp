@@ -129,11 +129,16 @@ __device__ __forceinline__ void hancock(const T u0[5], const T dm[5], const T dp
 // Only the side the contact speed selects is evaluated.  Rearranged for the
 // ALU, with the same value up to rounding:
 //   rho u = m (the normal momentum) in S*'s numerator;
-//   with q = 1 / (S_k - S*): star state = (rho_k, m_k, E_k) * g + extra terms,
-//   g = (S_k - u_k) q, and p_k / (rho_k (S_k - u_k)) * factor = p_k q;
-//   the supersonic cases use F_k + min(S_L, 0) (U*_L - U_L) (left) or
-//   F_k + max(S_R, 0) (U*_R - U_R) (right), whose correction vanishes
-//   exactly when the flux is F_L or F_R.
+//   the side k's flux is F_k + S_c (U*_k - U_k) with S_c = min(S_L, 0)
+//   (left) or max(S_R, 0) (right), whose correction vanishes exactly when
+//   the flux is F_L or F_R;
+//   with q = 1 / (S_k - S*) the star state is g U_k plus normal-momentum and
+//   energy terms, g = (S_k - u_k) q, so U*_k - U_k is formed from
+//   g - 1 = (S* - u_k) q directly (no cancellation where g is close to 1):
+//     mass and tangential momenta    (g - 1) U_k
+//     normal momentum                rho_k g S* - m_k
+//     energy                         (g - 1) E_k + (S* - u_k) (rho_k g S* + p_k q)
+//   (p_k / (rho_k (S_k - u_k)) times rho_k g is p_k q).
 template <typename T, int D>
 __device__ __forceinline__ void hllc(const T ul[5], const T ur[5], T f[5]) {
   using A = Arith<T>;
@@ -165,16 +170,15 @@ __device__ __forceinline__ void hllc(const T ul[5], const T ur[5], T f[5]) {
   T fk[5];
   flux<T, D>(uk, unk, pk, fk);
   const T q = A::recip(Sk - Ss);
-  const T g = (Sk - unk) * q;                // factor / rho_k
-  T us[5];
-  us[0] = uk[0] * g;
-  us[1] = uk[1] * g;
-  us[2] = uk[2] * g;
-  us[3] = uk[3] * g;
-  us[1 + D] = us[0] * Ss;
-  us[4] = fma_(Ss - unk, fma_(us[0], Ss, pk * q), uk[4] * g);
+  const T d = Ss - unk;                      // S* - u_k
+  const T gm = d * q;                        // g - 1
+  const T rs = fma_(uk[0], gm, uk[0]);       // rho*_k = rho_k g
+  const T sg = Sc * gm;
 #pragma unroll
-  for (int c = 0; c < 5; ++c) f[c] = fma_(Sc, us[c] - uk[c], fk[c]);
+  for (int c = 0; c < 4; ++c)
+    if (c != 1 + D) f[c] = fma_(sg, uk[c], fk[c]);
+  f[1 + D] = fma_(Sc, fma_(rs, Ss, -uk[1 + D]), fk[1 + D]);
+  f[4] = fma_(Sc, fma_(d, fma_(rs, Ss, pk * q), uk[4] * gm), fk[4]);
 }
 
 // Conservative update U' = U - lam (F_{i+1/2} - F_{i-1/2}).
@@ -185,10 +189,11 @@ __device__ __forceinline__ void update(const T u[5], T lam, const T fp[5], const
 }
 
 // Whole-wave lane shifts (DPP wave_shr:1 / wave_shl:1): lane l receives the
-// value of lane l - 1 (from_below) or l + 1 (from_above).  In FP32 the end
-// lanes receive zero, which lets the compiler fold a shift into the
-// instruction that consumes it; in FP64 they keep their own value.  Either
-// way the end lanes only ever feed discarded results.
+// value of lane l - 1 (from_below) or l + 1 (from_above).  The end lanes,
+// which have no source lane, receive zero (bound_ctrl): such a move needs no
+// copy of the old destination value first, and in FP32 the compiler can fold
+// it into the instruction that consumes it.  A 64-bit value moves as its two
+// 32-bit halves.  The end lanes only ever feed discarded results.
 __device__ __forceinline__ float from_below(float v) {
   const int i = __builtin_bit_cast(int, v);
   return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(i, 0x138, 0xF, 0xF, true));
@@ -197,21 +202,16 @@ __device__ __forceinline__ float from_above(float v) {
   const int i = __builtin_bit_cast(int, v);
   return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(i, 0x130, 0xF, 0xF, true));
 }
-__device__ __forceinline__ double shift64(double v, int ctrl_below) {
+template <int CTRL>
+__device__ __forceinline__ double shift64(double v) {
   const uint64_t u = __builtin_bit_cast(uint64_t, v);
   const int lo = (int)(uint32_t)u, hi = (int)(uint32_t)(u >> 32);
-  uint32_t a, b;
-  if (ctrl_below) {
-    a = (uint32_t)__builtin_amdgcn_update_dpp(lo, lo, 0x138, 0xF, 0xF, false);
-    b = (uint32_t)__builtin_amdgcn_update_dpp(hi, hi, 0x138, 0xF, 0xF, false);
-  } else {
-    a = (uint32_t)__builtin_amdgcn_update_dpp(lo, lo, 0x130, 0xF, 0xF, false);
-    b = (uint32_t)__builtin_amdgcn_update_dpp(hi, hi, 0x130, 0xF, 0xF, false);
-  }
+  const uint32_t a = (uint32_t)__builtin_amdgcn_mov_dpp(lo, CTRL, 0xF, 0xF, true);
+  const uint32_t b = (uint32_t)__builtin_amdgcn_mov_dpp(hi, CTRL, 0xF, 0xF, true);
   return __builtin_bit_cast(double, ((uint64_t)b << 32) | a);
 }
-__device__ __forceinline__ double from_below(double v) { return shift64(v, 1); }
-__device__ __forceinline__ double from_above(double v) { return shift64(v, 0); }
+__device__ __forceinline__ double from_below(double v) { return shift64<0x138>(v); }
+__device__ __forceinline__ double from_above(double v) { return shift64<0x130>(v); }
 
 // |u_d| + c for d = x, y, z; `bad` when rho <= 0, p <= 0 or a value is not finite.
 template <typename T>

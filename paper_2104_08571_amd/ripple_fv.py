@@ -163,7 +163,7 @@ def _declare(L):
         "ripple_fv_halo_exchange": (st, [vp, ctypes.c_int32, gp, ctypes.POINTER(vp),
                                          ctypes.c_int32, vp]),
         "ripple_fv_conserved_sums": (st, [vp, gp, vp, vp, vp]),
-        "ripple_fv_error_norms": (st, [vp, gp, vp, vp, vp, vp]),
+        "ripple_fv_error_norms": (st, [vp, gp, vp, vp, vp, vp, vp]),
         "ripple_fv_check": (st, [vp]),
         "ripple_fv_profile": (st, [vp, dp, ctypes.POINTER(ctypes.c_int64)]),
         "ripple_fv_status_string": (ctypes.c_char_p, [st]),
@@ -287,8 +287,9 @@ def ripple_fv_conserved_sums(ctx, g, u, sums_dev, stream=None):
     _check(lib().ripple_fv_conserved_sums(ctx, ctypes.byref(g), u, sums_dev, stream), ctx)
 
 
-def ripple_fv_error_norms(ctx, g, u, ref_dev, out_dev, stream=None):
-    _check(lib().ripple_fv_error_norms(ctx, ctypes.byref(g), u, ref_dev, out_dev, stream), ctx)
+def ripple_fv_error_norms(ctx, g, u, ref_dev, l1_dev, linf_dev, stream=None):
+    _check(lib().ripple_fv_error_norms(ctx, ctypes.byref(g), u, ref_dev, l1_dev, linf_dev, stream),
+           ctx)
 
 
 def ripple_fv_check(ctx):

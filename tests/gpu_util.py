@@ -74,10 +74,39 @@ def rel_l1(a, b):
     return np.array(out)
 
 
-def assert_parity(gpu, ref, tol, what=""):
+def rel_linf(a, b):
+    """Per-variable relative maximum error max|a - b| / scale: the scale of
+    rho and E is max|b| of that variable, the scale of each momentum
+    component the largest max|b| over the three components (a component that
+    vanishes in the reference, such as the transverse momenta of a planar
+    problem, is measured against the momentum the flow has).  0 when both
+    vanish, inf when only the reference does."""
+    mom = max(np.abs(b[c]).max() for c in (1, 2, 3))
+    out = []
+    for c in range(5):
+        den = mom if c in (1, 2, 3) else np.abs(b[c]).max()
+        num = np.abs(a[c] - b[c]).max()
+        out.append(num / den if den > 0 else (0.0 if num == 0 else np.inf))
+    return np.array(out)
+
+
+# Elementwise bound beside the relative L1 bound: ten times the L1 tolerance,
+# relative to the variable's largest magnitude.  An L1 sum alone lets a few
+# wrong cells through (one wrong row of a 512^3 grid is 4e-6 of its cells);
+# the largest errors measured after the full step counts stay a factor of
+# ten or more below this (FP32: 1.3e-5 on rho u after 50 steps at 512^3).
+LINF_FACTOR = 10.0
+
+
+def assert_parity(gpu, ref, tol, what="", tol_inf=None):
+    """Per-variable relative L1 <= tol and relative Linf (rel_linf) <=
+    tol_inf (default LINF_FACTOR * tol); returns the L1 errors."""
     assert np.isfinite(gpu).all(), f"{what}: non-finite values in the GPU result"
     err = rel_l1(gpu, ref)
     assert (err <= tol).all(), f"{what}: relative L1 per variable {err} exceeds {tol}"
+    tol_inf = LINF_FACTOR * tol if tol_inf is None else tol_inf
+    inf = rel_linf(gpu, ref)
+    assert (inf <= tol_inf).all(), f"{what}: relative Linf per variable {inf} exceeds {tol_inf}"
     return err
 
 

@@ -94,6 +94,23 @@ def test_grid_init_rejects(bad):
     assert e.value.status == R.E_INVALID
 
 
+def test_lane_offset_bound():
+    """Tiles address their lanes by 32-bit byte offsets from a wave-uniform
+    base; the rows form of the fused pass and the separate y sweep span up to
+    512 / n0 planes.  A thin x extent with large planes in AoS FP64 would
+    pass the cell-count bound but overflow the offsets: rejected.  The same
+    extents in SoA (one element per cell between lanes), and planar grids
+    (whose tiles stay within a row), are accepted."""
+    with pytest.raises(R.RippleFVError) as e:
+        R.make_grid((16, 90000, 32), dtype=R.F64, layout=R.AOS)
+    assert e.value.status == R.E_INVALID
+    R.make_grid((16, 90000, 32), dtype=R.F64, layout=R.SOA)
+    R.make_grid((9600, 6000, 1), dtype=R.F64, layout=R.AOS)
+    # the benchmark's largest grids stay far inside the bound
+    R.make_grid((1024, 1024, 1024), dtype=R.F64, layout=R.AOS)
+    R.make_grid((388, 384, 384), dtype=R.F32, layout=R.AOSOA, aosoa_w=64)
+
+
 def test_status_strings():
     assert R.ripple_fv_status_string(R.OK) == "ok"
     assert R.ripple_fv_status_string(R.E_NONPHYSICAL) == "non-physical state"

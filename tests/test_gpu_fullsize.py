@@ -1,13 +1,30 @@
-"""The workloads at their full sizes, in the launch configuration the
-benchmark times (persistent tile lists, default tiling, eager or graph).
+"""The workloads at their full sizes and full step counts, in the launch
+configuration the benchmark times (persistent tile lists, default tiling,
+eager launches or graph replay), against the FP64 oracle.
 
-Where the FP64 oracle finishes in seconds on the host it is run on the whole
-grid for the first steps.  For the full step counts the tests check
-properties that hold at any size: conservation to round-off on periodic
-grids (FP64 sums on the device), layout and launch-mode invariance, mirror
-symmetry, partitioned == monolithic, and oracle parity on sampled grids of the
-batch.
+Parity is checked after the stated number of steps, element by element
+(relative L1 and relative Linf per conserved variable, gpu_util.assert_parity):
+  - 256^3 FP64 periodic smooth field, 100 steps, AoS, SoA and AoSoA;
+  - 512^3 periodic smooth field, 50 steps, FP32 (the benchmark's run, graph
+    replay) and FP64, both against one 50-step oracle run;
+  - the 64-grid batch, 50 steps in a graph with the tuned layout and tiling,
+    on three sampled grids (smallest, largest, one between);
+  - the blast wave at 192^3, 100 steps, as one grid and as 2 x 2 x 2
+    sub-blocks with halo copies (FP64 and FP32), each against the oracle.
+The 768^3 blast as 2 x 2 x 2 sub-blocks (100 steps) is beyond the oracle's
+reach in a test (about 45 G cell-updates on the host); it is checked against
+the monolithic GPU run bitwise and for mirror symmetry, while the 192^3 case
+above pins the partitioned path to the oracle directly.  Conservation of the
+totals to round-off is checked on the periodic runs (FP64 sums on the device).
+
+The oracle runs in chunks of steps (each step takes its dt from the state it
+starts from, so chunks give the same states as one call) and reports each
+chunk on the terminal.  With RFV_REPORT_DIR set, the measured errors are also
+written there as JSON.
 """
+import json
+import os
+import sys
 import time
 
 import numpy as np
@@ -20,9 +37,46 @@ from paper_2104_08571_amd import ripple_fv as R
 
 pytestmark = pytest.mark.gpu
 
+TOL = {R.F32: 1e-5, R.F64: 1e-12}
+NAMES = ("rho", "mx", "my", "mz", "E")
 
-def log(msg):
-    print(f"[fullsize] {msg}", flush=True)
+
+def say(request, msg):
+    """A progress line on the terminal, outside pytest's output capture."""
+    line = f"[fullsize] {msg}"
+    capman = request.config.pluginmanager.getplugin("capturemanager")
+    if capman is None:
+        print(line, flush=True)
+        return
+    with capman.global_and_fixture_disabled():
+        sys.stdout.write("\n" + line + "\n")
+        sys.stdout.flush()
+
+
+def report(name, data):
+    d = os.environ.get("RFV_REPORT_DIR")
+    if d:
+        os.makedirs(d, exist_ok=True)
+        with open(os.path.join(d, f"errors_{name}.json"), "w") as f:
+            json.dump(data, f, indent=1)
+
+
+def errors(gpu, ref):
+    l1, linf = G.rel_l1(gpu, ref), G.rel_linf(gpu, ref)
+    return {n: {"rel_L1": float(a), "rel_Linf": float(b)} for n, a, b in zip(NAMES, l1, linf)}
+
+
+def oracle_steps(request, oracle, W, nsteps, dx, bc, label, chunk):
+    """The oracle advanced nsteps from primitive state W: (U, t)."""
+    U = oracle.prim_to_cons(W)
+    t, done, t0 = 0.0, 0, time.time()
+    while done < nsteps:
+        k = min(chunk, nsteps - done)
+        U, dt_sum, _ = oracle.run(U, k, dx, bc)
+        t += dt_sum
+        done += k
+        say(request, f"oracle {label}: step {done}/{nsteps} ({time.time() - t0:.0f} s)")
+    return U, t
 
 
 def sums(g, buf):
@@ -30,10 +84,6 @@ def sums(g, buf):
     R.ripple_fv_conserved_sums(G.ctx(), g, buf.data_ptr(), out.data_ptr(), G.stream())
     torch.cuda.synchronize()
     return out.cpu().numpy()
-
-
-def abs_sums(U):
-    return np.abs(U).reshape(5, -1).sum(1)
 
 
 def run_keep(grids, states, nsteps, flags=R.RUN_EAGER):
@@ -47,149 +97,192 @@ def run_keep(grids, states, nsteps, flags=R.RUN_EAGER):
     return a
 
 
-@pytest.mark.parametrize("layout", [R.AOS, R.SOA], ids=["aos", "soa"])
-def test_smooth_256_fp64(oracle, layout):
-    """256^3 FP64 periodic smooth field: parity with the oracle over the
-    first two steps on the full grid; 100 steps conserve all totals."""
-    n = (256, 256, 256)
-    W = ist.smooth_periodic(n, seed=2104, device="cuda")
-    g = R.make_grid(n, dtype=R.F64, layout=layout, bc=(1, 1, 1))
-    log(f"256^3 fp64 layout={layout}: oracle 2 steps")
-    t0 = time.time()
-    ref, t_ref, _ = oracle.run(oracle.prim_to_cons(W.cpu().numpy()), 2, G.unit_dx(n), [1, 1, 1])
-    log(f"oracle done in {time.time() - t0:.1f} s")
-    (gpu,), (t,) = G.run(g, W, 2)
-    err = G.assert_parity(gpu, ref, 1e-12, "256^3 fp64 2 steps")
-    assert abs(t - t_ref) <= 1e-13 * t_ref
-    log(f"rel L1 after 2 steps {err}")
-    del ref, gpu
-    U0 = G.export(g, G.load(g, W))
+def drift(g, buf, U0):
+    """Relative change of the interior totals against sum |U0|."""
+    return np.abs(sums(g, buf) - U0.reshape(5, -1).sum(1)) / np.abs(U0).reshape(5, -1).sum(1)
+
+
+# --- 256^3 FP64, 100 steps -------------------------------------------------
+
+N256 = (256, 256, 256)
+
+
+@pytest.fixture(scope="module")
+def ref256(request, oracle):
+    W = ist.smooth_periodic(N256, seed=2104).numpy()
+    return oracle_steps(request, oracle, W, 100, G.unit_dx(N256), [1, 1, 1], "256^3", 20)
+
+
+@pytest.mark.parametrize("layout", [(R.AOS, 0), (R.SOA, 0), (R.AOSOA, 32)],
+                         ids=["aos", "soa", "aosoa32"])
+def test_smooth_256_fp64_100_steps(request, ref256, layout):
+    ref, t_ref = ref256
+    W = ist.smooth_periodic(N256, seed=2104, device="cuda")
+    g = R.make_grid(N256, dtype=R.F64, layout=layout[0], aosoa_w=layout[1], bc=(1, 1, 1))
     buf = run_keep([g], [W], 100)[0]
-    s1 = sums(g, buf)
-    drift = np.abs(s1 - U0.reshape(5, -1).sum(1)) / abs_sums(U0)
-    log(f"100-step conservation drift {drift}")
-    assert (drift < 1e-13).all(), drift
+    t, _ = R.ripple_fv_batch_time(G.ctx(), [g])
+    U0 = G.export(g, G.load(g, W))
+    d = drift(g, buf, U0)
+    gpu = G.export(g, buf)
+    err = G.assert_parity(gpu, ref, TOL[R.F64], f"256^3 fp64 {layout} 100 steps")
+    assert abs(t[0] - t_ref) <= 1e-13 * t_ref
+    assert (d < 1e-13).all(), d
+    e = errors(gpu, ref)
+    say(request, f"256^3 fp64 {layout}: rel L1 {err}, conservation drift {d}")
+    report(f"smooth256_f64_{['aos', 'soa', 'aosoa'][layout[0]]}_100",
+           {"t": t[0], "t_oracle": t_ref, "errors": e, "drift": d.tolist()})
 
 
 def test_smooth_256_layouts_agree_at_100_steps():
-    n = (256, 256, 256)
-    W = ist.smooth_periodic(n, seed=2104, device="cuda")
     outs = []
+    W = ist.smooth_periodic(N256, seed=2104, device="cuda")
     for layout in (R.AOS, R.SOA):
-        g = R.make_grid(n, dtype=R.F64, layout=layout, bc=(1, 1, 1))
+        g = R.make_grid(N256, dtype=R.F64, layout=layout, bc=(1, 1, 1))
         outs.append(G.export(g, run_keep([g], [W], 100)[0]))
     assert np.array_equal(outs[0], outs[1])
 
 
-def test_smooth_512_fp32(oracle):
-    """512^3 FP32 periodic (the benchmark's workload and launch shape): one
-    step against the FP64 oracle on the whole grid; 50 steps keep the FP64
-    totals to round-off of FP32 storage."""
-    n = (512, 512, 512)
-    W = ist.smooth_periodic(n, seed=8571, device="cuda")
-    g = R.make_grid(n, dtype=R.F32, layout=R.SOA, bc=(1, 1, 1))
-    log("512^3 fp32: oracle 1 step")
-    t0 = time.time()
-    ref, t_ref, _ = oracle.run(oracle.prim_to_cons(W.cpu().numpy()), 1, G.unit_dx(n), [1, 1, 1])
-    log(f"oracle done in {time.time() - t0:.1f} s")
-    (gpu,), (t,) = G.run(g, W, 1)
-    err = G.assert_parity(gpu, ref, 1e-5, "512^3 fp32 1 step")
-    assert abs(t - t_ref) <= 1e-6 * t_ref
-    log(f"rel L1 after 1 step {err}")
-    del ref, gpu
-    U0 = G.export(g, G.load(g, W))
+# --- 512^3, 50 steps, FP32 and FP64 ----------------------------------------
+
+N512 = (512, 512, 512)
+
+
+@pytest.fixture(scope="module")
+def ref512(request, oracle):
+    W = ist.smooth_periodic(N512, seed=8571, device="cuda").cpu().numpy()
+    return oracle_steps(request, oracle, W, 50, G.unit_dx(N512), [1, 1, 1], "512^3", 5)
+
+
+@pytest.mark.parametrize("dtype", [R.F32, R.F64], ids=["f32", "f64"])
+def test_smooth_512_50_steps(request, ref512, dtype):
+    """The benchmark's workload (FP32, replayed from graphs) and its FP64
+    comparison run after 50 steps against the oracle; totals conserved to
+    round-off (FP64 sums of the FP32 state on the device)."""
+    ref, t_ref = ref512
+    W = ist.smooth_periodic(N512, seed=8571, device="cuda")
+    g = R.make_grid(N512, dtype=dtype, layout=R.SOA, bc=(1, 1, 1))
     buf = run_keep([g], [W], 50, flags=R.RUN_GRAPH)[0]
-    s1 = sums(g, buf)
-    drift = np.abs(s1 - U0.reshape(5, -1).sum(1)) / abs_sums(U0)
-    log(f"50-step conservation drift (FP32 storage, FP64 sums) {drift}")
-    assert (drift < 1e-8).all(), drift
-
-
-def test_smooth_512_fp64(oracle):
-    """512^3 FP64 periodic, the benchmark's FP64 comparison run (the fused
-    pass in its wave-strip form): one step against the oracle on the whole
-    grid; 20 steps keep the totals to FP64 round-off."""
-    n = (512, 512, 512)
-    W = ist.smooth_periodic(n, seed=8571, device="cuda")
-    g = R.make_grid(n, dtype=R.F64, layout=R.SOA, bc=(1, 1, 1))
-    log("512^3 fp64: oracle 1 step")
-    t0 = time.time()
-    ref, t_ref, _ = oracle.run(oracle.prim_to_cons(W.cpu().numpy()), 1, G.unit_dx(n), [1, 1, 1])
-    log(f"oracle done in {time.time() - t0:.1f} s")
-    (gpu,), (t,) = G.run(g, W, 1)
-    err = G.assert_parity(gpu, ref, 1e-12, "512^3 fp64 1 step")
-    assert abs(t - t_ref) <= 1e-14 * t_ref
-    log(f"rel L1 after 1 step {err}")
-    del ref, gpu
+    t, _ = R.ripple_fv_batch_time(G.ctx(), [g])
     U0 = G.export(g, G.load(g, W))
-    buf = run_keep([g], [W], 20, flags=R.RUN_GRAPH)[0]
-    s1 = sums(g, buf)
-    drift = np.abs(s1 - U0.reshape(5, -1).sum(1)) / abs_sums(U0)
-    log(f"20-step conservation drift (FP64) {drift}")
-    assert (drift < 1e-13).all(), drift
+    del W
+    d = drift(g, buf, U0)
+    del U0
+    gpu = G.export(g, buf)
+    del buf
+    torch.cuda.empty_cache()
+    name = "f32" if dtype == R.F32 else "f64"
+    e = errors(gpu, ref)
+    say(request, f"512^3 {name} after 50 steps: {json.dumps(e)}; drift {d}")
+    report(f"smooth512_{name}_50", {"t": t[0], "t_oracle": t_ref, "errors": e,
+                                     "drift": d.tolist()})
+    G.assert_parity(gpu, ref, TOL[dtype], f"512^3 {name} 50 steps")
+    assert abs(t[0] - t_ref) <= (1e-6 if dtype == R.F32 else 1e-13) * t_ref
+    assert (d < (1e-8 if dtype == R.F32 else 1e-13)).all(), d
 
 
-def test_batch_64_grids(oracle):
-    """64 grids with extents drawn from {32, 48, ..., 192}: batched graph
-    replay == per-grid launches bitwise; three sampled grids match the oracle."""
+# --- batch of 64 grids, 50 steps -------------------------------------------
+
+def test_batch_64_grids_50_steps(request, oracle):
+    """64 grids with extents drawn from {32, 48, ..., 192}: the tuned layout
+    and tiling replayed from graphs for 50 steps; equal bitwise to the
+    default configuration and to one launch per grid; three sampled grids
+    match the oracle after the 50 steps."""
     ext = ist.batch_extents(64, seed=42)
-    grids = [R.make_grid(e, dtype=R.F32, layout=R.SOA, bc=(1, 1, 1)) for e in ext]
+    base = [R.make_grid(e, dtype=R.F32, layout=R.SOA, bc=(1, 1, 1)) for e in ext]
+    tuned = list(R.ripple_fv_batch_tune(G.ctx(), base, G.stream()))
+    say(request, f"batch tuned: layout {tuned[0].layout} w {tuned[0].aosoa_w} tiling "
+                 f"{(tuned[0].x_block, tuned[0].yz_block, tuned[0].yz_segment, tuned[0].persist, tuned[0].yz_cols, tuned[0].split_xy)}")
     states = [ist.smooth_periodic(e, seed=1000 + i, device="cuda") for i, e in enumerate(ext)]
-    log(f"batch: {sum(e[0] * e[1] * e[2] for e in ext) / 1e6:.1f} M cells")
-    batched, tb = G.run(grids, states, 2, flags=R.RUN_GRAPH)
-    per_grid, tp = G.run(grids, states, 2, flags=R.RUN_PER_GRID)
-    assert tb == tp
-    for a, b in zip(batched, per_grid):
-        assert np.array_equal(a, b)
+    graph, tg = G.run(tuned, states, 50, flags=R.RUN_GRAPH)
     sizes = [e[0] * e[1] * e[2] for e in ext]
     for i in (int(np.argmin(sizes)), int(np.argmax(sizes)), 17):
-        ref, t_ref, _ = oracle.run(oracle.prim_to_cons(states[i].cpu().numpy()), 2,
+        ref, t_ref, _ = oracle.run(oracle.prim_to_cons(states[i].cpu().numpy()), 50,
                                    G.unit_dx(ext[i]), [1, 1, 1])
-        G.assert_parity(batched[i], ref, 1e-5, f"batch grid {i} {ext[i]}")
-        assert abs(tb[i] - t_ref) <= 1e-6 * t_ref
-    del batched, per_grid
-    bufs = run_keep(grids, states, 50, flags=R.RUN_GRAPH)
-    for i in (0, 33):
-        U0 = G.export(grids[i], G.load(grids[i], states[i]))
-        drift = np.abs(sums(grids[i], bufs[i]) - U0.reshape(5, -1).sum(1)) / abs_sums(U0)
-        assert (drift < 1e-8).all(), (i, drift)
+        err = G.assert_parity(graph[i], ref, TOL[R.F32], f"batch grid {i} {ext[i]} 50 steps")
+        assert abs(tg[i] - t_ref) <= 1e-6 * t_ref
+        say(request, f"batch grid {i} {ext[i]}: rel L1 after 50 steps {err}")
+    default, td = G.run(base, states, 50, flags=R.RUN_GRAPH)
+    per_grid, tp = G.run(base, states, 50, flags=R.RUN_PER_GRID)
+    assert tg == td == tp
+    for a, b, c in zip(graph, default, per_grid):
+        assert np.array_equal(a, b) and np.array_equal(a, c)
 
 
-def test_blast_192_fp64(oracle):
-    """Blast wave at 192^3 in FP64 against the oracle (5 steps)."""
-    n = (192, 192, 192)
-    W = ist.blast(n, device="cuda")
-    g = R.make_grid(n, dtype=R.F64, layout=R.SOA)
-    ref, t_ref, _ = oracle.run(oracle.prim_to_cons(W.cpu().numpy()), 5, G.unit_dx(n), [0, 0, 0])
-    (gpu,), (t,) = G.run(g, W, 5)
-    err = G.assert_parity(gpu, ref, 1e-12, "blast 192^3")
-    assert abs(t - t_ref) <= 1e-13 * t_ref
-    log(f"blast 192^3 rel L1 {err}")
+# --- blast wave, 100 steps -------------------------------------------------
+
+N192 = (192, 192, 192)
 
 
-def test_partition_768_fp32():
+@pytest.fixture(scope="module")
+def ref_blast192(request, oracle):
+    W = ist.blast(N192).numpy()
+    return oracle_steps(request, oracle, W, 100, G.unit_dx(N192), [0, 0, 0], "blast 192^3", 25)
+
+
+def _blocks(whole, parts, n):
+    subs = R.ripple_fv_partition(whole, parts)
+    origins, states = [], []
+    for i, s in enumerate(subs):
+        a, b, c = i % parts[0], (i // parts[0]) % parts[1], i // (parts[0] * parts[1])
+        o = [k * (nn // p) + min(k, nn % p) for k, nn, p in zip((a, b, c), n, parts)]
+        origins.append(o)
+        states.append(ist.blast(list(s.n), origin=o, n_global=n, device="cuda"))
+    return subs, origins, states
+
+
+def _assemble(subs, origins, outs, n):
+    U = np.empty((5, n[2], n[1], n[0]))
+    for s, o, X in zip(subs, origins, outs):
+        U[:, o[2]:o[2] + s.n[2], o[1]:o[1] + s.n[1], o[0]:o[0] + s.n[0]] = X
+    return U
+
+
+@pytest.mark.parametrize("case", ["f64_whole", "f64_2x2x2", "f32_2x2x2"])
+def test_blast_192_100_steps(request, ref_blast192, case):
+    """Blast wave at 192^3 after 100 steps against the oracle: one grid in
+    FP64, and 2 x 2 x 2 sub-blocks with on-device halo copies in FP64 and
+    FP32 (the partitioned path compared with the oracle directly)."""
+    ref, t_ref = ref_blast192
+    dtype = R.F64 if case.startswith("f64") else R.F32
+    whole = R.make_grid(N192, dtype=dtype, layout=R.SOA)
+    if case == "f64_whole":
+        (gpu,), (t,) = G.run(whole, ist.blast(N192, device="cuda"), 100)
+        ts = [t]
+    else:
+        subs, origins, states = _blocks(whole, (2, 2, 2), N192)
+        outs, ts = G.run(subs, states, 100)
+        gpu = _assemble(subs, origins, outs, N192)
+        assert len(set(ts)) == 1
+    err = G.assert_parity(gpu, ref, TOL[dtype], f"blast 192^3 {case} 100 steps")
+    assert abs(ts[0] - t_ref) <= (1e-6 if dtype == R.F32 else 1e-13) * t_ref
+    say(request, f"blast 192^3 {case}: rel L1 after 100 steps {err}")
+    report(f"blast192_{case}_100", {"t": ts[0], "t_oracle": t_ref, "errors": errors(gpu, ref)})
+
+
+def test_partition_768_fp32_100_steps(request):
     """768^3 FP32 blast as 2 x 2 x 2 sub-blocks of 384^3 with on-device halo
-    copies == the monolithic 768^3 grid, bitwise; the result is mirror
-    symmetric about the centre planes."""
+    copies == the monolithic 768^3 grid, bitwise, after the 100 steps; the
+    result is mirror symmetric about the centre planes."""
     n = (768, 768, 768)
     whole = R.make_grid(n, dtype=R.F32, layout=R.SOA)
-    subs = R.ripple_fv_partition(whole, (2, 2, 2))
-    steps = 3
-    log("768^3 monolithic")
+    steps = 100
+    say(request, "768^3 monolithic, 100 steps")
     Wfull = ist.blast(n, device="cuda")
     mono = run_keep([whole], [Wfull], steps)[0]
     del Wfull
     torch.cuda.empty_cache()
-    log("768^3 as 2x2x2 sub-blocks")
-    origins = [((i % 2) * 384, ((i // 2) % 2) * 384, (i // 4) * 384) for i in range(8)]
-    states = [ist.blast((384, 384, 384), origin=o, n_global=n, device="cuda") for o in origins]
+    say(request, "768^3 as 2x2x2 sub-blocks, 100 steps")
+    subs, origins, states = _blocks(whole, (2, 2, 2), n)
     parts = run_keep(subs, states, steps)
     del states
     ref = G.export(whole, mono)
+    del mono
+    torch.cuda.empty_cache()
     for s, o, buf in zip(subs, origins, parts):
         U = G.export(s, buf)
         part = ref[:, o[2]:o[2] + 384, o[1]:o[1] + 384, o[0]:o[0] + 384]
         assert np.array_equal(U, part), o
+    del parts
     # mirror symmetry on bands through the centre (x and y mirrors on a band of
     # z planes, the z mirror on a band of y rows)
     scale = np.abs(ref[:, 380:388]).max(axis=(1, 2, 3), keepdims=True)

@@ -50,6 +50,28 @@ def test_tiling_invariance_bitwise(dtype):
             assert np.array_equal(U, ref[0]), tl
 
 
+@pytest.mark.parametrize("layout,w", [(R.SOA, 0), (R.AOSOA, 32), (R.AOS, 0)],
+                         ids=["soa", "aosoa32", "aos"])
+@pytest.mark.parametrize("split", [1, 0], ids=["separate", "fused"])
+def test_yz_columns_per_thread_bitwise(layout, w, split):
+    """FP32 y and z sweeps advancing one or two adjacent x cells per thread
+    (the two-cell groups move each component as one 8-byte access) give the
+    same bits, on rows of odd and even length, with the separate and the
+    fused x-y pass; the lane shifts of the wave-strip form (whose end lanes
+    receive zero) against the rows form are covered by test_gpu_fused."""
+    for shape, bc in (((37, 29, 23), (1, 0, 1)), ((64, 18, 40), (0, 1, 1)), ((17, 33, 9), (1, 1, 0))):
+        W = smooth(shape, seed=13)
+        outs = []
+        for cols in (1, 2):
+            g = R.make_grid(shape, dtype=R.F32, layout=layout, aosoa_w=w, bc=bc,
+                            tiling=(0, 0, 0, 0, cols, split))
+            outs.append(G.run(g, W, 3))
+        (U1,), (t1,) = outs[0]
+        (U2,), (t2,) = outs[1]
+        assert t1 == t2, (shape, cols)
+        assert np.array_equal(U1, U2), (shape, layout, split)
+
+
 def _batch(dtype, layout=R.SOA, aosoa_w=0):
     shapes = [(32, 48, 40), (17, 9, 23), (64, 16, 32)]
     bcs = [(1, 1, 1), (0, 0, 0), (1, 0, 1)]

@@ -121,19 +121,34 @@ def test_conserved_sums_and_norms():
     sums = torch.zeros(5, dtype=torch.float64, device="cuda")
     R.ripple_fv_conserved_sums(G.ctx(), g, buf.data_ptr(), sums.data_ptr(), G.stream())
     ref = torch.as_tensor(U + 0.01 * np.sin(np.arange(U.size)).reshape(U.shape)).cuda()
-    out = torch.zeros(20, dtype=torch.float64, device="cuda")
-    R.ripple_fv_error_norms(G.ctx(), g, buf.data_ptr(), ref.data_ptr(), out.data_ptr(), G.stream())
+    l1 = torch.zeros(5, dtype=torch.float64, device="cuda")
+    linf = torch.zeros(5, dtype=torch.float64, device="cuda")
+    R.ripple_fv_error_norms(G.ctx(), g, buf.data_ptr(), ref.data_ptr(), l1.data_ptr(),
+                            linf.data_ptr(), G.stream())
     torch.cuda.synchronize()
     # totals can cancel to ~0 (zero-mean momenta): compare against the sum of |U|
     scale = np.abs(U).reshape(5, -1).sum(1)
     assert (np.abs(sums.cpu().numpy() - U.reshape(5, -1).sum(1)) <= 1e-13 * scale).all()
-    o = out.cpu().numpy().reshape(5, 4)
     r = ref.cpu().numpy()
+    l1, linf = l1.cpu().numpy(), linf.cpu().numpy()
     for c in range(5):
-        np.testing.assert_allclose(o[c, 0], np.abs(U[c] - r[c]).sum(), rtol=1e-12)
-        np.testing.assert_allclose(o[c, 1], np.abs(r[c]).sum(), rtol=1e-12)
-        assert o[c, 2] == np.abs(U[c] - r[c]).max()
-        assert o[c, 3] == np.abs(r[c]).max()
+        np.testing.assert_allclose(l1[c], np.abs(U[c] - r[c]).sum() / np.abs(r[c]).sum(),
+                                   rtol=1e-12)
+        # maxima are exact, so the ratio is one correctly rounded division
+        assert linf[c] == np.abs(U[c] - r[c]).max() / np.abs(r[c]).max()
+    # a vanishing reference: 0 where the state matches it, else +inf
+    zero = torch.zeros_like(ref)
+    R.ripple_fv_error_norms(G.ctx(), g, buf.data_ptr(), zero.data_ptr(), l1.data_ptr(),
+                            linf.data_ptr(), G.stream())
+    torch.cuda.synchronize()
+    l1, linf = l1.cpu().numpy(), linf.cpu().numpy()
+    assert np.isinf(l1).all() and np.isinf(linf).all()
+    Z = G.buffer(g)
+    Zs = G.load(g, np.zeros_like(U), Z, variables=R.CONSERVED)
+    R.ripple_fv_error_norms(G.ctx(), g, Zs.data_ptr(), zero.data_ptr(), l1.data_ptr(),
+                            linf.data_ptr(), G.stream())
+    torch.cuda.synchronize()
+    assert not l1.cpu().numpy().any() and not linf.cpu().numpy().any()
 
 
 def test_import_export_roundtrip_and_convert():

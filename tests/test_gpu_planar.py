@@ -27,7 +27,7 @@ TOL = {R.F32: 1e-5, R.F64: 1e-12}
 
 
 def assert_parity_momentum_scaled(gpu, ref, tol, what):
-    """Relative L1 per variable, with the three momenta measured against the
+    """Relative L1 and Linf per variable, with the three momenta measured against the
     total momentum sum(|m_x| + |m_y| + |m_z|): early in the shock-bubble run
     m_y is zero in exact arithmetic, and so in the oracle, while rounding
     leaves ulp-level values on the device (an FP64 contact is stationary only
@@ -38,6 +38,9 @@ def assert_parity_momentum_scaled(gpu, ref, tol, what):
         den = mom if c in (1, 2, 3) else np.abs(ref[c]).sum()
         err = np.abs(gpu[c] - ref[c]).sum() / den
         assert err <= tol, f"{what}: variable {c} relative L1 {err:.3e} exceeds {tol}"
+    # elementwise, with the momenta scaled alike (gpu_util.rel_linf)
+    inf = G.rel_linf(gpu, ref)
+    assert (inf <= G.LINF_FACTOR * tol).all(), f"{what}: relative Linf {inf}"
 
 
 def oracle_run(oracle, W, nsteps, dx, bc):
