@@ -35,8 +35,8 @@ PEAK_VALU_TFLOPS = 78.6
 # Arithmetic of one cell update along one axis, counted from the formulas the
 # kernels evaluate (add, sub, mul, min, max, median, reciprocal and square root
 # 1 each, fused multiply-add 2): slopes and Hancock half step 89, HLLC face
-# flux 84, conservative update 15.
-FLOPS_PER_CELL_AXIS = 188
+# flux 78 (the star-state correction formed from g - 1), conservative update 15.
+FLOPS_PER_CELL_AXIS = 182
 CSRC = os.path.join(ROOT, "paper_2104_08571_amd", "csrc")
 PROFILES = os.path.join(ROOT, "profiles")
 
@@ -197,6 +197,59 @@ def run_partition_workload(steps, warmup):
     del a, b
     torch.cuda.empty_cache()
     return out
+
+
+def run_layout_workload(n, steps, warmup, layouts):
+    """The 256^3 FP64 periodic smooth field (seed 2104) in each cell layout:
+    `steps` steps replayed from hipGraphs with the state resident in HBM, and
+    per-kernel times from a profiled eager run of a few steps.  Bytes per step
+    are reported for the two passes the step makes (20 s per cell: x-y and z,
+    each reading and writing the state once) and for three separate sweeps
+    (30 s per cell, the accounting of a step that makes three passes)."""
+    import torch
+
+    from paper_2104_08571_amd import initial_states as ist
+    from paper_2104_08571_amd import ripple_fv as R
+
+    lays = {"soa": (R.SOA, 0), "aos": (R.AOS, 0), "aosoa16": (R.AOSOA, 16),
+            "aosoa32": (R.AOSOA, 32), "aosoa64": (R.AOSOA, 64)}
+    ctx = R.ripple_fv_create(0)
+    stream = torch.cuda.current_stream().cuda_stream
+    W = ist.smooth_periodic((n, n, n), seed=2104, device="cuda")
+    cells = n ** 3
+    rows = []
+    try:
+        for name in layouts:
+            g = R.make_grid((n, n, n), dtype=R.F64, layout=lays[name][0], aosoa_w=lays[name][1],
+                            bc=(R.PERIODIC,) * 3)
+            a = torch.empty(g.bytes, dtype=torch.uint8, device="cuda")
+            b = torch.empty(g.bytes, dtype=torch.uint8, device="cuda")
+            pa, pb = [a.data_ptr()], [b.data_ptr()]
+            R.ripple_fv_import(ctx, g, W.data_ptr(), R.PRIMITIVE, a.data_ptr(), stream)
+            R.ripple_fv_run_batch(ctx, [g], pa, pb, warmup, 0.9, R.RUN_EAGER, stream)
+            R.ripple_fv_profile(ctx)
+            R.ripple_fv_run_batch(ctx, [g], pa, pb, 5, 0.9, R.RUN_PROFILE, stream)
+            torch.cuda.synchronize()
+            prof = R.ripple_fv_profile(ctx)
+            R.ripple_fv_run_batch(ctx, [g], pa, pb, steps, 0.9, R.RUN_GRAPH, stream)  # capture
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            R.ripple_fv_run_batch(ctx, [g], pa, pb, steps, 0.9, R.RUN_GRAPH, stream)
+            torch.cuda.synchronize()
+            secs = time.perf_counter() - t0
+            row = {"layout": name, "steps": steps, "ms_per_step": round(secs / steps * 1e3, 4),
+                   "gcell_updates_per_s": round(cells * steps / secs / 1e9, 3),
+                   "GBps_two_passes": round(20 * 8 * cells * steps / secs / 1e9, 1),
+                   "GBps_three_sweeps": round(30 * 8 * cells * steps / secs / 1e9, 1),
+                   "kernel_ms": {k: round(ms / c, 4) for k, (ms, c) in prof.items() if c},
+                   "status": R.ripple_fv_check(ctx)}
+            rows.append(row)
+            print(f"[bench] layouts 256^3 f64 {name}: {row}", file=sys.stderr, flush=True)
+            del a, b
+            torch.cuda.empty_cache()
+    finally:
+        R.ripple_fv_destroy(ctx)
+    return {"workload": f"euler3d_smooth_periodic_{n}cubed_f64", "cells": cells, "results": rows}
 
 
 def run_shock_bubble_workload(sizes, dtypes, steps, warmup):
@@ -497,7 +550,12 @@ def main():
                     help="oracle steps timed for cpu_baseline (0 = skip); 3 steps of the "
                          "512^3 workload are about 12 s on 16 host threads")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the batched and partitioned workloads")
+                    help="skip the batched and partitioned workloads and the 256^3 layout leg")
+    ap.add_argument("--layouts", default="aos,soa,aosoa16,aosoa32,aosoa64",
+                    help="cell layouts of the 256^3 FP64 leg (100 steps each)")
+    ap.add_argument("--layout-steps", type=int, default=100)
+    ap.add_argument("--layouts-only", action="store_true",
+                    help="run only the 256^3 FP64 layout leg (prints its JSON)")
     ap.add_argument("--no-force2d", action="store_true",
                     help="skip the 2D FORCE flux-difference leg")
     ap.add_argument("--force2d-only", action="store_true",
@@ -532,6 +590,10 @@ def main():
     sb_args = ([(6400, 4000), (9600, 6000)], ["f32", "f64"], args.shock_bubble_steps, args.warmup)
     pt_args = ([int(v) for v in args.particles_sizes.split(",")], args.particles_dtypes.split(","),
                args.particles_layouts.split(","), max(args.steps, 5), args.warmup)
+    lay_args = (256, args.layout_steps, args.warmup, args.layouts.split(","))
+    if args.layouts_only:
+        print(json.dumps({"layouts_256_f64": run_layout_workload(*lay_args)}), flush=True)
+        return
     if args.particles_only:
         print(json.dumps({"particle_update": run_particle_workload(*pt_args)}), flush=True)
         return
@@ -587,12 +649,13 @@ def main():
     ceiling = copy_ceiling()
     print(f"[bench] plain copy: {ceiling}", file=sys.stderr, flush=True)
 
-    batch = part = None
+    batch = part = lays = None
     if not args.no_extra:
         batch = run_batch_workload(args.steps, args.warmup)
         print(f"[bench] batch 64 grids: {batch}", file=sys.stderr, flush=True)
         part = run_partition_workload(args.steps, args.warmup)
         print(f"[bench] partition 768^3: {part}", file=sys.stderr, flush=True)
+        lays = run_layout_workload(*lay_args)
 
     sb = None
     if not args.no_shock_bubble:
@@ -634,6 +697,20 @@ def main():
         "cpu_baseline": base,
         "copy_ceiling": ceiling,
     }
+    # the long per-size tables first, so that the end of the line (what a
+    # log tail shows) holds the 3D results and the summary
+    if f2 is not None:
+        out["force2d_flux_difference"] = f2
+    if pt is not None:
+        out["particle_update"] = pt
+    if sb is not None:
+        out["shock_bubble_2d"] = sb
+    if batch is not None:
+        out["batch_64_grids_f32"] = batch
+    if part is not None:
+        out["partition_768_f32_2x2x2"] = part
+    if lays is not None:
+        out["layouts_256_f64"] = lays
     if f64 is not None:
         out["f64"] = {"value": round(f64["gcell_updates_per_s"], 4), "unit": "Gcell-updates/s",
                       "ms_per_step": round(f64["ms_per_step"], 4),
@@ -642,16 +719,31 @@ def main():
                       "kernel_ms": f64["kernel_ms"],
                       "roofline": roofline(f64, measured_traffic(
                           f64["dominant"], f"{workload}_f64_{args.layout}"))}
+    summary = {
+        f"f32_{n}": {"gcell_updates_per_s": round(f32["gcell_updates_per_s"], 2),
+                     "ms_per_step": round(f32["ms_per_step"], 4),
+                     "graph_ms_per_step": round(f32["graph_ms_per_step"], 4),
+                     "GBps_two_passes": round(f32["algorithmic_GBps_step"] * 2 / 3, 1),
+                     "kernel_ms": {k: v for k, v in f32["kernel_ms"].items() if v}},
+    }
+    if f64 is not None:
+        summary[f"f64_{n}"] = {"gcell_updates_per_s": round(f64["gcell_updates_per_s"], 2),
+                               "ms_per_step": round(f64["ms_per_step"], 4),
+                               "GBps_two_passes": round(f64["algorithmic_GBps_step"] * 2 / 3, 1),
+                               "kernel_ms": {k: v for k, v in f64["kernel_ms"].items() if v}}
     if batch is not None:
-        out["batch_64_grids_f32"] = batch
+        summary["batch_64_grids_f32"] = {
+            "graph": batch["batched_graph"]["gcell_updates_per_s"],
+            "eager": batch["batched_eager"]["gcell_updates_per_s"],
+            "per_grid": batch["per_grid"]["gcell_updates_per_s"], "chosen": batch["chosen"]}
     if part is not None:
-        out["partition_768_f32_2x2x2"] = part
-    if sb is not None:
-        out["shock_bubble_2d"] = sb
-    if f2 is not None:
-        out["force2d_flux_difference"] = f2
-    if pt is not None:
-        out["particle_update"] = pt
+        summary["partition_768_f32_2x2x2"] = {"gcell_updates_per_s": part["gcell_updates_per_s"],
+                                              "halo_ms_per_step": part["halo_ms_per_step"]}
+    if lays is not None:
+        summary["layouts_256_f64_gcell_updates_per_s"] = {
+            r["layout"]: r["gcell_updates_per_s"] for r in lays["results"]}
+    out["summary"] = summary
+    print("[bench] summary: " + json.dumps(summary), file=sys.stderr, flush=True)
     print(json.dumps(out), flush=True)
 
 

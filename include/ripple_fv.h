@@ -323,6 +323,16 @@ ripple_fv_status ripple_fv_error_norms(ripple_fv_ctx* ctx, const ripple_fv_grid*
                                        const void* u, const double* ref_dev, double* l1_dev,
                                        double* linf_dev, void* stream);
 
+/* Plain device copy of `bytes` (a multiple of 16) from src to dst, each
+ * byte read once and written once in 16-byte accesses: the reference
+ * stream against which the sweeps' HBM bandwidth is measured, and the
+ * known-size program that calibrates hardware byte counters.  flags:
+ * RIPPLE_FV_COPY_NONTEMPORAL marks the stores non-temporal.  src and dst
+ * must not overlap (E_INVALID). */
+#define RIPPLE_FV_COPY_NONTEMPORAL 1
+ripple_fv_status ripple_fv_stream_copy(ripple_fv_ctx* ctx, void* dst, const void* src,
+                                       int64_t bytes, int32_t flags, void* stream);
+
 /* Wait for the device, then report and clear the sticky non-physical flag:
  * E_NONPHYSICAL if any kernel since the last check met rho <= 0, p <= 0 or
  * a non-finite value (wave-speed kernel and the last sweep of every step),

@@ -26,11 +26,14 @@ constexpr int MAX_PLANS = 16;
 constexpr int GRAPH_MAX_STEPS = 64;  // steps captured in one graph
 constexpr int MAX_GRAPHS = 4;        // cached graphs per plan
 
-struct Plan {
+// Launch description of a batch over storage owned elsewhere (a cached Plan
+// owns heap vectors and one device allocation; other storage can back the
+// same view).  The enqueue functions read only this.
+struct PlanCore {
   int n = 0;
   int dtype = 0, lay = 0;
   Tiling tl{};
-  std::vector<ripple_fv_grid> grids;
+  const ripple_fv_grid* grids = nullptr;  // host descriptors [n]
   bool fused = false;                   // x and y sweeps as one pass
   int seg_xy = 0;                       // rows per tile of the fused pass
   int xmode = XM_ROWS;                  // form of the fused pass
@@ -39,11 +42,15 @@ struct Plan {
   // the step returns the state to its first buffer (else the passes alternate
   // the two buffers from step to step)
   bool in_place() const { return fused || (planar && !planar_fused); }
-  std::vector<int64_t> tiles[5];        // prefix: x, y, z, wave-speed, fused x-y tiles
-  std::vector<HaloTask> halo[3];
+  // host: tile prefix sums [n + 1] of the x, y, z, wave-speed and fused x-y
+  // launches; halo copy tasks per axis (at most 2 n each); descriptors with
+  // the current buffer pointers [n]
+  const int64_t* tiles[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  const HaloTask* halo[3] = {nullptr, nullptr, nullptr};
+  int nhalo[3] = {0, 0, 0};
   int64_t halo_area[3] = {0, 0, 0};
-  // device workspace (one allocation) and its views
-  void* dmem = nullptr;
+  const DevGrid* h_grids = nullptr;
+  // device copies and per-grid slots
   DevGrid* d_grids = nullptr;
   int64_t* d_tiles[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   HaloTask* d_halo[3] = {nullptr, nullptr, nullptr};
@@ -51,8 +58,61 @@ struct Plan {
   double* d_t = nullptr;
   double* d_dt = nullptr;
   unsigned long long* d_s = nullptr;
+
+  Work work(unsigned int* flag) const {
+    Work w;
+    w.grids = d_grids;
+    w.ngrids = n;
+    w.pad_ = 0;
+    w.lam = d_lam;
+    w.t = d_t;
+    w.dt = d_dt;
+    w.s_acc = d_s;
+    w.flag = flag;
+    return w;
+  }
+};
+
+// Byte offsets of the device workspace of a batch of n grids with nhalo[]
+// halo tasks per axis: descriptors, tile prefix sums, halo tasks, then the
+// per-grid dt / lambda / time / wave-speed slots (each part 256-byte aligned).
+struct WsLayout {
+  size_t grids, tiles[5], halo[3], lam, t, dt, s, total;
+};
+
+WsLayout ws_layout(int n, const int nhalo[3]) {
+  auto align = [](size_t v) { return (v + 255) & ~size_t(255); };
+  WsLayout L;
+  size_t off = 0;
+  L.grids = off; off = align(off + sizeof(DevGrid) * n);
+  for (int k = 0; k < 5; ++k) { L.tiles[k] = off; off = align(off + sizeof(int64_t) * (n + 1)); }
+  for (int k = 0; k < 3; ++k) { L.halo[k] = off; off = align(off + sizeof(HaloTask) * (nhalo[k] + 1)); }
+  L.lam = off; off = align(off + sizeof(double) * 3 * n);
+  L.t = off; off = align(off + sizeof(double) * n);
+  L.dt = off; off = align(off + sizeof(double) * n);
+  L.s = off; off = align(off + sizeof(unsigned long long) * 3 * n);
+  L.total = off;
+  return L;
+}
+
+void ws_bind(PlanCore& P, char* base, const WsLayout& L) {
+  P.d_grids = reinterpret_cast<DevGrid*>(base + L.grids);
+  for (int k = 0; k < 5; ++k) P.d_tiles[k] = reinterpret_cast<int64_t*>(base + L.tiles[k]);
+  for (int k = 0; k < 3; ++k) P.d_halo[k] = reinterpret_cast<HaloTask*>(base + L.halo[k]);
+  P.d_lam = reinterpret_cast<double*>(base + L.lam);
+  P.d_t = reinterpret_cast<double*>(base + L.t);
+  P.d_dt = reinterpret_cast<double*>(base + L.dt);
+  P.d_s = reinterpret_cast<unsigned long long*>(base + L.s);
+}
+
+// A cached plan: owns the host arrays, the device workspace and the graphs.
+struct Plan : PlanCore {
+  std::vector<ripple_fv_grid> grid_store;
+  std::vector<int64_t> tile_store[5];
+  std::vector<HaloTask> halo_store[3];
+  std::vector<DevGrid> h_grid_store;
+  void* dmem = nullptr;                 // device workspace (one allocation)
   // descriptor staging for buffer-pointer updates
-  std::vector<DevGrid> h_grids;
   DevGrid* h_pinned = nullptr;
   hipEvent_t upload_done = nullptr;
   bool upload_pending = false;
@@ -78,18 +138,6 @@ struct Plan {
     }
     if (h_pinned) hipHostFree(h_pinned);
     if (dmem) hipFree(dmem);
-  }
-  Work work(unsigned int* flag) const {
-    Work w;
-    w.grids = d_grids;
-    w.ngrids = n;
-    w.pad_ = 0;
-    w.lam = d_lam;
-    w.t = d_t;
-    w.dt = d_dt;
-    w.s_acc = d_s;
-    w.flag = flag;
-    return w;
   }
 };
 
@@ -150,7 +198,7 @@ ripple_fv_status grid_check(const ripple_fv_grid* g, int64_t pitch[3], int64_t* 
   }
   if (!valid_block(g->x_block, {0, 128, 256}) || !valid_block(g->yz_block, {0, 64, 128, 256}) ||
       g->yz_segment < 0 || (g->yz_segment > 0 && g->yz_segment < 4) || g->yz_segment > 4096 ||
-      g->persist < 0 || g->persist > 64 || !valid_block(g->yz_cols, {0, 1, 2}) ||
+      g->persist < 0 || g->persist > 64 || !valid_block(g->yz_cols, {0, 1, 2, 4}) ||
       !valid_block(g->split_xy, {0, 1, 2, 3}) || g->reserved != 0) {
     *why = "bad tiling knobs";
     return RIPPLE_FV_E_INVALID;
@@ -208,11 +256,13 @@ Tiling tiling_of(const ripple_fv_grid& g) {
   t.persist = g.persist;
   // two x cells per y/z thread pays off where it widens the accesses (FP32
   // SoA/AoSoA); FP64 always runs one (two FP64 cells per thread do not fit
-  // the register file without spilling)
+  // the register file without spilling); four (16-byte accesses) only where
+  // a component's cells are adjacent, so AoS takes two for four
   if (g.dtype == RIPPLE_FV_F64)
     t.yz_cols = 1;
   else
     t.yz_cols = g.yz_cols ? g.yz_cols : (g.layout != RIPPLE_FV_AOS ? 2 : 1);
+  if (t.yz_cols == 4 && g.layout == RIPPLE_FV_AOS) t.yz_cols = 2;
   t.split_xy = g.split_xy;
   return t;
 }
@@ -320,57 +370,56 @@ ripple_fv_status validate_batch(ripple_fv_ctx* ctx, int n, const ripple_fv_grid*
   return RIPPLE_FV_OK;
 }
 
-ripple_fv_status build_plan(ripple_fv_ctx* ctx, int n, const ripple_fv_grid* grids, Plan** out) {
-  const std::string key = plan_key(n, grids);
-  auto it = ctx->plans.find(key);
-  if (it != ctx->plans.end()) {
-    *out = it->second.get();
-    return RIPPLE_FV_OK;
-  }
-  std::unique_ptr<Plan> P(new Plan());
-  P->n = n;
-  P->dtype = grids[0].dtype;
-  P->lay = lay_of(grids[0]);
-  P->tl = tiling_of(grids[0]);
-  P->grids.assign(grids, grids + n);
+// The launch shape of a validated batch, computed on the host into caller
+// storage (no allocation): tiles[k] hold n + 1 prefix sums each, halo[k] up
+// to 2 n tasks each, h_grids n descriptors (buffer pointers left null).
+void plan_shape(PlanCore& P, int n, const ripple_fv_grid* grids, int64_t* const tiles[5],
+                HaloTask* const halo[3], DevGrid* h_grids) {
+  P.n = n;
+  P.dtype = grids[0].dtype;
+  P.lay = lay_of(grids[0]);
+  P.tl = tiling_of(grids[0]);
+  P.grids = grids;
   // Grids one cell thick in z skip the z sweep.  Their x and y sweeps run
   // as one pass in the wave-strip form (whatever split_xy other than 1 asks
   // for: the rows form does not reduce wave speeds), which is then the whole
   // step and reduces the next step's wave speeds; with split_xy = 1 or rows
   // under XY_MIN_NX cells they run separately and the y sweep reduces them.
-  P->planar = true;
-  for (int g = 0; g < n; ++g) P->planar = P->planar && grids[g].n[2] == 1;
-  P->fused = P->tl.split_xy != 1 && !P->planar;
-  P->planar_fused = P->tl.split_xy != 1 && P->planar;
+  P.planar = true;
+  for (int g = 0; g < n; ++g) P.planar = P.planar && grids[g].n[2] == 1;
+  P.fused = P.tl.split_xy != 1 && !P.planar;
+  P.planar_fused = P.tl.split_xy != 1 && P.planar;
   for (int g = 0; g < n; ++g) {
-    P->fused = P->fused && xy_eligible(grids[g]);
-    P->planar_fused = P->planar_fused && xy_eligible(grids[g]);
+    P.fused = P.fused && xy_eligible(grids[g]);
+    P.planar_fused = P.planar_fused && xy_eligible(grids[g]);
   }
   // The fused pass marches tiles of seg_xy rows along y.  Where that leaves
   // fewer than XY_MIN_TILES tiles (thin or two-dimensional grids) the
   // segments shrink, down to 16 rows (or the configured segment if that is
   // shorter), so that the launch fills the device.
-  P->seg_xy = P->tl.yz_segment;
-  if (P->fused) P->xmode = xy_mode(P->dtype, grids, n, P->tl.split_xy);
-  if (P->planar_fused) P->xmode = XM_WAVES;
-  if (P->fused || P->planar_fused) {
-    int64_t tiles = 0;
-    for (int g = 0; g < n; ++g) tiles += tiles_xy(grids[g], P->seg_xy, P->xmode);
-    if (tiles < XY_MIN_TILES)
-      P->seg_xy = (int)std::max<int64_t>(std::min(16, P->seg_xy),
-                                         (int64_t)P->seg_xy * tiles / XY_MIN_TILES);
+  P.seg_xy = P.tl.yz_segment;
+  P.xmode = XM_ROWS;
+  if (P.fused) P.xmode = xy_mode(P.dtype, grids, n, P.tl.split_xy);
+  if (P.planar_fused) P.xmode = XM_WAVES;
+  if (P.fused || P.planar_fused) {
+    int64_t count = 0;
+    for (int g = 0; g < n; ++g) count += tiles_xy(grids[g], P.seg_xy, P.xmode);
+    if (count < XY_MIN_TILES)
+      P.seg_xy = (int)std::max<int64_t>(std::min(16, P.seg_xy),
+                                        (int64_t)P.seg_xy * count / XY_MIN_TILES);
   }
-  for (int k = 0; k < 5; ++k) P->tiles[k].assign(n + 1, 0);
+  for (int k = 0; k < 5; ++k) tiles[k][0] = 0;
   for (int g = 0; g < n; ++g) {
-    P->tiles[4][g + 1] = P->tiles[4][g] + (P->fused || P->planar_fused ? tiles_xy(grids[g], P->seg_xy, P->xmode) : 0);
-    P->tiles[0][g + 1] = P->tiles[0][g] + tiles_x(grids[g], P->tl.x_block);
-    P->tiles[1][g + 1] = P->tiles[1][g] + tiles_yz(grids[g], 1, P->tl.yz_block, P->tl.yz_segment,
-                                                   P->tl.yz_cols);
-    P->tiles[2][g + 1] = P->tiles[2][g] + tiles_yz(grids[g], 2, P->tl.yz_block, P->tl.yz_segment,
-                                                   P->tl.yz_cols);
-    P->tiles[3][g + 1] = P->tiles[3][g] + tiles_ws(grids[g]);
+    tiles[4][g + 1] = tiles[4][g] + (P.fused || P.planar_fused ? tiles_xy(grids[g], P.seg_xy, P.xmode) : 0);
+    tiles[0][g + 1] = tiles[0][g] + tiles_x(grids[g], P.tl.x_block);
+    tiles[1][g + 1] = tiles[1][g] + tiles_yz(grids[g], 1, P.tl.yz_block, P.tl.yz_segment, P.tl.yz_cols);
+    tiles[2][g + 1] = tiles[2][g] + tiles_yz(grids[g], 2, P.tl.yz_block, P.tl.yz_segment, P.tl.yz_cols);
+    tiles[3][g + 1] = tiles[3][g] + tiles_ws(grids[g]);
   }
+  for (int k = 0; k < 5; ++k) P.tiles[k] = tiles[k];
   for (int axis = 0; axis < 3; ++axis) {
+    int count = 0;
+    P.halo_area[axis] = 0;
     for (int g = 0; g < n; ++g) {
       const ripple_fv_grid& G = grids[g];
       for (int side = 0; side < 2; ++side) {
@@ -381,17 +430,17 @@ ripple_fv_status build_plan(ripple_fv_ctx* ctx, int n, const ripple_fv_grid* gri
         t.src = h;
         t.side = side;
         t.pad_ = 0;
-        P->halo[axis].push_back(t);
+        halo[axis][count++] = t;
         const int64_t area = (int64_t)G.n[axis == 0 ? 1 : 0] * G.n[axis == 2 ? 1 : 2];
-        P->halo_area[axis] = std::max(P->halo_area[axis], area);
+        P.halo_area[axis] = std::max(P.halo_area[axis], area);
       }
     }
+    P.nhalo[axis] = count;
+    P.halo[axis] = halo[axis];
   }
-  // host descriptors (buffer pointers filled per call)
-  P->h_grids.resize(n);
   for (int g = 0; g < n; ++g) {
     const ripple_fv_grid& G = grids[g];
-    DevGrid& D = P->h_grids[g];
+    DevGrid& D = h_grids[g];
     std::memset(&D, 0, sizeof(D));
     for (int d = 0; d < 3; ++d) {
       D.n[d] = G.n[d];
@@ -410,38 +459,47 @@ ripple_fv_status build_plan(ripple_fv_ctx* ctx, int n, const ripple_fv_grid* gri
     D.ptot = cell_slots(G);
     D.ox = G.x_origin;
     D.group = group_of(G, g);
+    D.nbr_x[0] = G.nbr[0];
+    D.nbr_x[1] = G.nbr[1];
   }
+  P.h_grids = h_grids;
+}
+
+ripple_fv_status build_plan(ripple_fv_ctx* ctx, int n, const ripple_fv_grid* grids, Plan** out) {
+  const std::string key = plan_key(n, grids);
+  auto it = ctx->plans.find(key);
+  if (it != ctx->plans.end()) {
+    *out = it->second.get();
+    return RIPPLE_FV_OK;
+  }
+  std::unique_ptr<Plan> P(new Plan());
+  P->grid_store.assign(grids, grids + n);
+  int64_t* tiles[5];
+  HaloTask* halo[3];
+  for (int k = 0; k < 5; ++k) {
+    P->tile_store[k].assign(n + 1, 0);
+    tiles[k] = P->tile_store[k].data();
+  }
+  for (int k = 0; k < 3; ++k) {
+    P->halo_store[k].resize(2 * (size_t)n);
+    halo[k] = P->halo_store[k].data();
+  }
+  P->h_grid_store.resize(n);
+  plan_shape(*P, n, P->grid_store.data(), tiles, halo, P->h_grid_store.data());
   // device workspace
-  auto align = [](size_t v) { return (v + 255) & ~size_t(255); };
-  size_t off = 0;
-  const size_t o_grids = off; off = align(off + sizeof(DevGrid) * n);
-  size_t o_tiles[5];
-  for (int k = 0; k < 5; ++k) { o_tiles[k] = off; off = align(off + sizeof(int64_t) * (n + 1)); }
-  size_t o_halo[3];
-  for (int k = 0; k < 3; ++k) { o_halo[k] = off; off = align(off + sizeof(HaloTask) * (P->halo[k].size() + 1)); }
-  const size_t o_lam = off; off = align(off + sizeof(double) * 3 * n);
-  const size_t o_t = off; off = align(off + sizeof(double) * n);
-  const size_t o_dt = off; off = align(off + sizeof(double) * n);
-  const size_t o_s = off; off = align(off + sizeof(unsigned long long) * 3 * n);
-  if (hipMalloc(&P->dmem, off) != hipSuccess) {
+  const WsLayout L = ws_layout(n, P->nhalo);
+  if (hipMalloc(&P->dmem, L.total) != hipSuccess) {
     (void)hipGetLastError();
     return fail(ctx, RIPPLE_FV_E_NOMEM, "plan workspace allocation failed");
   }
-  char* base = static_cast<char*>(P->dmem);
-  P->d_grids = reinterpret_cast<DevGrid*>(base + o_grids);
-  for (int k = 0; k < 5; ++k) P->d_tiles[k] = reinterpret_cast<int64_t*>(base + o_tiles[k]);
-  for (int k = 0; k < 3; ++k) P->d_halo[k] = reinterpret_cast<HaloTask*>(base + o_halo[k]);
-  P->d_lam = reinterpret_cast<double*>(base + o_lam);
-  P->d_t = reinterpret_cast<double*>(base + o_t);
-  P->d_dt = reinterpret_cast<double*>(base + o_dt);
-  P->d_s = reinterpret_cast<unsigned long long*>(base + o_s);
+  ws_bind(*P, static_cast<char*>(P->dmem), L);
   for (int k = 0; k < 5; ++k)
-    HIP_OR_FAIL(ctx, hipMemcpy(P->d_tiles[k], P->tiles[k].data(), sizeof(int64_t) * (n + 1),
+    HIP_OR_FAIL(ctx, hipMemcpy(P->d_tiles[k], P->tiles[k], sizeof(int64_t) * (n + 1),
                                hipMemcpyHostToDevice));
   for (int k = 0; k < 3; ++k)
-    if (!P->halo[k].empty())
-      HIP_OR_FAIL(ctx, hipMemcpy(P->d_halo[k], P->halo[k].data(),
-                                 sizeof(HaloTask) * P->halo[k].size(), hipMemcpyHostToDevice));
+    if (P->nhalo[k])
+      HIP_OR_FAIL(ctx, hipMemcpy(P->d_halo[k], P->halo[k], sizeof(HaloTask) * P->nhalo[k],
+                                 hipMemcpyHostToDevice));
   HIP_OR_FAIL(ctx, hipMemset(P->d_lam, 0, sizeof(double) * 3 * n));
   HIP_OR_FAIL(ctx, hipMemset(P->d_t, 0, sizeof(double) * n));
   HIP_OR_FAIL(ctx, hipMemset(P->d_dt, 0, sizeof(double) * n));
@@ -468,13 +526,14 @@ ripple_fv_status upload_buffers(ripple_fv_ctx* ctx, Plan* P, void* const* a, voi
   for (int g = 0; g < P->n; ++g) {
     void* na = a[g];
     void* nb = b ? b[g] : nullptr;
-    if (P->h_grids[g].buf[0] != na || P->h_grids[g].buf[1] != nb) changed = true;
-    P->h_grids[g].buf[0] = na;
-    P->h_grids[g].buf[1] = nb;
+    DevGrid& D = P->h_grid_store[g];
+    if (D.buf[0] != na || D.buf[1] != nb) changed = true;
+    D.buf[0] = na;
+    D.buf[1] = nb;
   }
   if (!changed) return RIPPLE_FV_OK;
   if (P->upload_pending) HIP_OR_FAIL(ctx, hipEventSynchronize(P->upload_done));
-  std::memcpy(P->h_pinned, P->h_grids.data(), sizeof(DevGrid) * P->n);
+  std::memcpy(P->h_pinned, P->h_grid_store.data(), sizeof(DevGrid) * P->n);
   HIP_OR_FAIL(ctx, hipMemcpyAsync(P->d_grids, P->h_pinned, sizeof(DevGrid) * P->n,
                                   hipMemcpyHostToDevice, s));
   HIP_OR_FAIL(ctx, hipEventRecord(P->upload_done, s));
@@ -536,7 +595,7 @@ struct Launcher {
 
 // Enqueue one sweep along `axis` for every grid (persistent launch over the
 // batch's tile list, or one launch per grid).
-ripple_fv_status enqueue_sweep(ripple_fv_ctx* ctx, Plan* P, Launcher& L, int axis, int in, int out,
+ripple_fv_status enqueue_sweep(ripple_fv_ctx* ctx, const PlanCore* P, Launcher& L, int axis, int in, int out,
                                int fuse_s, bool per_grid) {
   SweepParams sp{};
   sp.w = P->work(ctx->flag);
@@ -548,7 +607,7 @@ ripple_fv_status enqueue_sweep(ripple_fv_ctx* ctx, Plan* P, Launcher& L, int axi
   hipEvent_t e1 = nullptr;
   ripple_fv_status st = L.begin(RIPPLE_FV_K_SWEEP_X + axis, &e1);
   if (st) return st;
-  const std::vector<int64_t>& pre = P->tiles[axis];
+  const int64_t* pre = P->tiles[axis];
   if (per_grid) {
     for (int g = 0; g < P->n; ++g) {
       sp.tiles.first = pre[g];
@@ -566,7 +625,7 @@ ripple_fv_status enqueue_sweep(ripple_fv_ctx* ctx, Plan* P, Launcher& L, int axi
 }
 
 // Enqueue the fused x-then-y sweep (plans whose grids all allow it).
-ripple_fv_status enqueue_sweep_xy(ripple_fv_ctx* ctx, Plan* P, Launcher& L, int in, int out,
+ripple_fv_status enqueue_sweep_xy(ripple_fv_ctx* ctx, const PlanCore* P, Launcher& L, int in, int out,
                                   int fuse_s, bool per_grid) {
   SweepParams sp{};
   sp.w = P->work(ctx->flag);
@@ -575,11 +634,14 @@ ripple_fv_status enqueue_sweep_xy(ripple_fv_ctx* ctx, Plan* P, Launcher& L, int 
   sp.seg = P->seg_xy;
   sp.fuse_s = fuse_s;
   sp.xmode = P->xmode;
+  sp.link_x = 0;
+  for (int g = 0; g < P->n; ++g)
+    if (P->h_grids[g].mode[0] == FACE_HALO || P->h_grids[g].mode[1] == FACE_HALO) sp.link_x = 1;
   sp.tiles.tile_start = P->d_tiles[4];
   hipEvent_t e1 = nullptr;
   ripple_fv_status st = L.begin(RIPPLE_FV_K_SWEEP_XY, &e1);
   if (st) return st;
-  const std::vector<int64_t>& pre = P->tiles[4];
+  const int64_t* pre = P->tiles[4];
   if (per_grid) {
     for (int g = 0; g < P->n; ++g) {
       sp.tiles.first = pre[g];
@@ -596,26 +658,26 @@ ripple_fv_status enqueue_sweep_xy(ripple_fv_ctx* ctx, Plan* P, Launcher& L, int 
   return L.end(e1);
 }
 
-ripple_fv_status enqueue_halo(ripple_fv_ctx* ctx, Plan* P, Launcher& L, int axis, int buf,
+ripple_fv_status enqueue_halo(ripple_fv_ctx* ctx, const PlanCore* P, Launcher& L, int axis, int buf,
                               int ext = 0) {
-  if (P->halo[axis].empty()) return RIPPLE_FV_OK;
+  if (P->nhalo[axis] == 0) return RIPPLE_FV_OK;
   hipEvent_t e1 = nullptr;
   ripple_fv_status st = L.begin(RIPPLE_FV_K_HALO, &e1);
   if (st) return st;
   LAUNCH_OR_FAIL(ctx, launch_halo(P->dtype, P->lay, P->work(ctx->flag), buf, axis, ext,
-                                  P->d_halo[axis], (int)P->halo[axis].size(),
+                                  P->d_halo[axis], P->nhalo[axis],
                                   P->halo_area[axis], L.s));
   return L.end(e1);
 }
 
-ripple_fv_status enqueue_wavespeed(ripple_fv_ctx* ctx, Plan* P, Launcher& L, int buf,
+ripple_fv_status enqueue_wavespeed(ripple_fv_ctx* ctx, const PlanCore* P, Launcher& L, int buf,
                                    unsigned long long* s_out, bool per_grid) {
   hipEvent_t e1 = nullptr;
   ripple_fv_status st = L.begin(RIPPLE_FV_K_WAVESPEED, &e1);
   if (st) return st;
   TileRange tr;
   tr.tile_start = P->d_tiles[3];
-  const std::vector<int64_t>& pre = P->tiles[3];
+  const int64_t* pre = P->tiles[3];
   Tiling tl = P->tl;
   if (per_grid) {
     for (int g = 0; g < P->n; ++g) {
@@ -633,7 +695,7 @@ ripple_fv_status enqueue_wavespeed(ripple_fv_ctx* ctx, Plan* P, Launcher& L, int
   return L.end(e1);
 }
 
-ripple_fv_status enqueue_dt(ripple_fv_ctx* ctx, Plan* P, Launcher& L, double cfl, double fixed_dt,
+ripple_fv_status enqueue_dt(ripple_fv_ctx* ctx, const PlanCore* P, Launcher& L, double cfl, double fixed_dt,
                             int reset_s, double* dt_out) {
   hipEvent_t e1 = nullptr;
   ripple_fv_status st = L.begin(RIPPLE_FV_K_DT, &e1);
@@ -645,15 +707,16 @@ ripple_fv_status enqueue_dt(ripple_fv_ctx* ctx, Plan* P, Launcher& L, double cfl
 // One step starting from buffer `cur`: dt, then x (cur -> oth), y (oth -> cur),
 // z (cur -> oth) with the new state's wave speeds folded into the slots; or,
 // in a fused plan, x-y (cur -> oth) and z (oth -> cur).
-ripple_fv_status enqueue_step(ripple_fv_ctx* ctx, Plan* P, Launcher& L, int cur, double cfl,
+ripple_fv_status enqueue_step(ripple_fv_ctx* ctx, const PlanCore* P, Launcher& L, int cur, double cfl,
                               double fixed_dt, double* dt_out, bool per_grid) {
   const int oth = 1 - cur;
   ripple_fv_status st = enqueue_dt(ctx, P, L, cfl, fixed_dt, 1, dt_out);
   if (P->fused) {
     // the fused pass x-sweeps the y padding rows itself: they take the raw
-    // neighbour rows first, then the x copy covers them too (corner cells)
+    // neighbour rows first; its lanes past a linked x face read the x
+    // neighbour's cells directly (its y padding rows holding the corners), so
+    // no x copy precedes it
     if (!st) st = enqueue_halo(ctx, P, L, 1, cur);
-    if (!st) st = enqueue_halo(ctx, P, L, 0, cur, HALO);
     if (!st) st = enqueue_sweep_xy(ctx, P, L, cur, oth, 0, per_grid);
     if (!st) st = enqueue_halo(ctx, P, L, 2, oth);
     if (!st) st = enqueue_sweep(ctx, P, L, 2, oth, cur, 1, per_grid);
@@ -663,7 +726,6 @@ ripple_fv_status enqueue_step(ripple_fv_ctx* ctx, Plan* P, Launcher& L, int cur,
     // a sweep along a one-cell axis changes nothing (see below): the x-y
     // pass is the whole step and reduces the next step's wave speeds
     if (!st) st = enqueue_halo(ctx, P, L, 1, cur);
-    if (!st) st = enqueue_halo(ctx, P, L, 0, cur, HALO);
     if (!st) st = enqueue_sweep_xy(ctx, P, L, cur, oth, 1, per_grid);
     return st;
   }
@@ -685,7 +747,7 @@ ripple_fv_status enqueue_step(ripple_fv_ctx* ctx, Plan* P, Launcher& L, int cur,
 
 // After an odd number of separate-sweep steps the state is in the work
 // buffers: copy it back.
-ripple_fv_status enqueue_copy_back(ripple_fv_ctx* ctx, Plan* P, hipStream_t s) {
+ripple_fv_status enqueue_copy_back(ripple_fv_ctx* ctx, const PlanCore* P, hipStream_t s) {
   for (int g = 0; g < P->n; ++g)
     HIP_OR_FAIL(ctx, hipMemcpyAsync(P->h_grids[g].buf[0], P->h_grids[g].buf[1], P->grids[g].bytes,
                                     hipMemcpyDeviceToDevice, s));
@@ -1093,6 +1155,22 @@ ripple_fv_status ripple_fv_error_norms(ripple_fv_ctx* ctx, const ripple_fv_grid*
   return RIPPLE_FV_OK;
 }
 
+ripple_fv_status ripple_fv_stream_copy(ripple_fv_ctx* ctx, void* dst, const void* src,
+                                       int64_t bytes, int32_t flags, void* stream) {
+  ripple_fv_status st = set_device(ctx);
+  if (st) return st;
+  if (bytes < 0 || bytes % 16 != 0) return fail(ctx, RIPPLE_FV_E_INVALID, "bytes must be a multiple of 16");
+  if (flags & ~1) return fail(ctx, RIPPLE_FV_E_INVALID, "unknown flags");
+  if (bytes == 0) return RIPPLE_FV_OK;
+  if ((st = ptr_ok(ctx, src, bytes, 16, "src"))) return st;
+  if ((st = ptr_ok(ctx, dst, bytes, 16, "dst"))) return st;
+  const char* a = static_cast<const char*>(src);
+  const char* b = static_cast<const char*>(dst);
+  if (a < b + bytes && b < a + bytes) return fail(ctx, RIPPLE_FV_E_INVALID, "src and dst overlap");
+  HIP_OR_FAIL(ctx, launch_stream_copy(dst, src, bytes, flags & 1, (hipStream_t)stream));
+  return RIPPLE_FV_OK;
+}
+
 ripple_fv_status ripple_fv_check(ripple_fv_ctx* ctx) {
   ripple_fv_status st = set_device(ctx);
   if (st) return st;
@@ -1148,14 +1226,28 @@ struct TuneBufs {
   }
 };
 
-// Time `steps` steps of the batch described by `cand` on a synthetic smooth
-// state; returns milliseconds (or a status through *st).
-double time_candidate(ripple_fv_ctx* ctx, std::vector<ripple_fv_grid>& cand, double* W,
-                      hipStream_t s, ripple_fv_status* st) {
+// Timing of one candidate: median and spread (largest minus smallest) of
+// TUNE_REPEATS replays of a captured graph of TUNE_STEPS steps, in ms per
+// replay.  Graph replay is the launch mode of a batch's long runs, and the
+// median of several replays keeps one noisy timing from deciding the pick.
+constexpr int TUNE_STEPS = 4;
+constexpr int TUNE_REPEATS = 5;
+
+struct TuneTime {
+  double median = 0.0;
+  double spread = 0.0;
+};
+
+// Time the batch described by `cand` on a synthetic smooth state (one eager
+// warm-up step, one untimed graph run that captures the graph, then the
+// timed replays).
+TuneTime time_candidate(ripple_fv_ctx* ctx, std::vector<ripple_fv_grid>& cand, double* W,
+                        hipStream_t s, ripple_fv_status* st) {
   *st = RIPPLE_FV_OK;
+  TuneTime out;
   const int n = (int)cand.size();
   for (auto& g : cand) {
-    if (ripple_fv_grid_init(&g)) { *st = fail(ctx, RIPPLE_FV_E_INVALID, "tuner candidate"); return 0; }
+    if (ripple_fv_grid_init(&g)) { *st = fail(ctx, RIPPLE_FV_E_INVALID, "tuner candidate"); return out; }
   }
   TuneBufs B;
   B.a.assign(n, nullptr);
@@ -1164,30 +1256,46 @@ double time_candidate(ripple_fv_ctx* ctx, std::vector<ripple_fv_grid>& cand, dou
     if (hipMalloc(&B.a[g], cand[g].bytes) != hipSuccess || hipMalloc(&B.b[g], cand[g].bytes) != hipSuccess) {
       (void)hipGetLastError();
       *st = fail(ctx, RIPPLE_FV_E_NOMEM, "tuner buffer allocation failed");
-      return 0;
+      return out;
     }
     hipError_t e = launch_tune_state(W, cand[g].n, s);
     if (e == hipSuccess) e = launch_import(desc_of(cand[g], B.a[g]), W, 1, s);
-    if (e != hipSuccess) { *st = fail(ctx, RIPPLE_FV_E_DEVICE, hipGetErrorString(e)); return 0; }
+    if (e != hipSuccess) { *st = fail(ctx, RIPPLE_FV_E_DEVICE, hipGetErrorString(e)); return out; }
   }
-  if ((*st = run(ctx, n, cand.data(), B.a.data(), B.b.data(), 1, 0.9, 0.0, nullptr, 0, s))) return 0;
-  hipEvent_t e0, e1;
-  hipEventCreate(&e0);
-  hipEventCreate(&e1);
-  hipEventRecord(e0, s);
-  *st = run(ctx, n, cand.data(), B.a.data(), B.b.data(), 4, 0.9, 0.0, nullptr, 0, s);
-  hipEventRecord(e1, s);
-  hipEventSynchronize(e1);
-  float ms = 0.f;
-  hipEventElapsedTime(&ms, e0, e1);
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  auto drop_plan = [&]() {
+    // the candidate's plan refers to buffers that are about to be freed
+    const std::string key = plan_key(n, cand.data());
+    ctx->plans.erase(key);
+    for (auto it = ctx->plan_order.begin(); it != ctx->plan_order.end(); ++it)
+      if (*it == key) { ctx->plan_order.erase(it); break; }
+  };
+  *st = run(ctx, n, cand.data(), B.a.data(), B.b.data(), 1, 0.9, 0.0, nullptr, 0, s);
+  if (!*st)
+    *st = run(ctx, n, cand.data(), B.a.data(), B.b.data(), TUNE_STEPS, 0.9, 0.0, nullptr,
+              RIPPLE_FV_RUN_GRAPH, s);
+  std::vector<double> ms;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (!*st && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+    *st = fail(ctx, RIPPLE_FV_E_DEVICE, "tuner events");
+  for (int r = 0; r < TUNE_REPEATS && !*st; ++r) {
+    hipEventRecord(e0, s);
+    *st = run(ctx, n, cand.data(), B.a.data(), B.b.data(), TUNE_STEPS, 0.9, 0.0, nullptr,
+              RIPPLE_FV_RUN_GRAPH, s);
+    hipEventRecord(e1, s);
+    hipEventSynchronize(e1);
+    float t = 0.f;
+    hipEventElapsedTime(&t, e0, e1);
+    ms.push_back(t);
+  }
+  if (e0) hipEventDestroy(e0);
+  if (e1) hipEventDestroy(e1);
   hipDeviceSynchronize();
-  // drop the candidate's plan: its buffers are about to be freed
-  ctx->plans.erase(plan_key(n, cand.data()));
-  for (auto it = ctx->plan_order.begin(); it != ctx->plan_order.end(); ++it)
-    if (*it == plan_key(n, cand.data())) { ctx->plan_order.erase(it); break; }
-  return ms;
+  drop_plan();
+  if (*st) return out;
+  std::sort(ms.begin(), ms.end());
+  out.median = ms[ms.size() / 2];
+  out.spread = ms.back() - ms.front();
+  return out;
 }
 
 }  // namespace
@@ -1220,15 +1328,21 @@ extern "C" ripple_fv_status ripple_fv_batch_tune(ripple_fv_ctx* ctx, int32_t n,
     (void)hipGetLastError();
     return fail(ctx, RIPPLE_FV_E_NOMEM, "tuner state allocation failed");
   }
+  // The incumbent starts as the default configuration (SoA, library
+  // defaults) and is replaced only by a candidate whose median beats it by
+  // more than the larger of the two timings' spreads, so noise alone never
+  // moves the pick away from the default.
   std::vector<ripple_fv_grid> best = base;
-  double best_ms = 1e300;
+  TuneTime best_t;
+  bool have_best = false;
   auto consider = [&](std::vector<ripple_fv_grid> cand) -> ripple_fv_status {
     ripple_fv_status s2;
-    const double ms = time_candidate(ctx, cand, W, s, &s2);
+    const TuneTime t = time_candidate(ctx, cand, W, s, &s2);
     if (s2) return s2;
-    if (ms < best_ms) {
-      best_ms = ms;
+    if (!have_best || t.median < best_t.median - std::max(best_t.spread, t.spread)) {
+      best_t = t;
       best = cand;
+      have_best = true;
     }
     return RIPPLE_FV_OK;
   };
@@ -1258,7 +1372,7 @@ extern "C" ripple_fv_status ripple_fv_batch_tune(ripple_fv_ctx* ctx, int32_t n,
       st = consider(with([&](ripple_fv_grid& g) { g.yz_block = yb; g.yz_segment = sg; }));
     }
   // 4. x cells per y/z thread, fused or separate x and y sweeps
-  for (int cols : {1, 2}) {
+  for (int cols : {1, 2, 4}) {
     if (st || base[0].dtype == RIPPLE_FV_F64) break;  // FP64 runs one cell per thread
     st = consider(with([&](ripple_fv_grid& g) { g.yz_cols = cols; }));
   }

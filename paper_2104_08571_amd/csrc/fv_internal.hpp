@@ -27,6 +27,7 @@ struct DevGrid {
   double dx[3];
   int32_t group;       // index of the grid whose wave-speed slot and dt this grid uses
   int32_t ox;          // padded x index of interior x = 0
+  int32_t nbr_x[2];    // batch index of the sub-block linked at -x / +x (-1: none)
 };
 
 // Per-batch device workspace handed to the kernels.
@@ -56,7 +57,7 @@ struct SweepParams {
   int32_t seg;         // cells per thread along the sweep axis (y, z sweeps)
   int32_t fuse_s;      // accumulate wave speeds of the output (z sweep)
   int32_t xmode;       // fused pass: XM_ROWS or XM_WAVES
-  int32_t pad_;
+  int32_t link_x;      // fused pass: some grid has an x face linked to a sub-block
 };
 
 struct HaloTask {
@@ -116,6 +117,9 @@ hipError_t launch_dt(const Work& w, double cfl, double fixed_dt, int reset_s, do
 hipError_t launch_halo(int dtype, int lay, const Work& w, int buf, int axis, int ext,
                        const HaloTask* tasks, int ntasks, int64_t max_area, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s);
+// Plain 16-byte-access device copy of `bytes` (a multiple of 16); nt: the
+// stores carry the non-temporal hint.
+hipError_t launch_stream_copy(void* dst, const void* src, int64_t bytes, int nt, hipStream_t s);
 hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t s);
 
 // Generic (runtime layout) transfer and diagnostics kernels.

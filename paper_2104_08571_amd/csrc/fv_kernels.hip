@@ -191,6 +191,11 @@ __global__ void __launch_bounds__(NT) k_sweep_x(SweepParams p, const DevGrid* __
 #ifndef RFV_YZ_RING
 #define RFV_YZ_RING 5
 #endif
+// Tile order of the y/z sweeps: 0 = segments of one column chunk fastest;
+// 1 = column chunks fastest (the tiles in flight cover a band of segments).
+#ifndef RFV_YZ_ORDER
+#define RFV_YZ_ORDER 0
+#endif
 template <typename T, int LAY, int D, bool FUSE, int COLS>
 __global__ void __launch_bounds__(256) k_sweep_yz(SweepParams p, const DevGrid* __restrict__ grids,
                                                   const int64_t* __restrict__ tile_start,
@@ -209,10 +214,16 @@ __global__ void __launch_bounds__(256) k_sweep_yz(SweepParams p, const DevGrid* 
     const uint32_t nb = G.n[D == 1 ? 2 : 1];
     const int nd = G.n[D];
     const int nseg = (nd + p.seg - 1) / p.seg;
-    const int64_t chunk = lt / nseg;
-    const int s = (int)(lt - chunk * nseg);
     const uint32_t npr = (na + COLS - 1) / COLS;  // column groups per row
     const uint32_t ngroups = npr * nb;
+#if RFV_YZ_ORDER
+    const int64_t nchunk = (ngroups + nt - 1) / nt;
+    const int s = (int)(lt / nchunk);
+    const int64_t chunk = lt - (int64_t)s * nchunk;
+#else
+    const int64_t chunk = lt / nseg;
+    const int s = (int)(lt - chunk * nseg);
+#endif
     const uint32_t f0 = (uint32_t)(chunk * nt);
     const uint32_t fl = f0 + tid;
     const bool active = fl < ngroups;
@@ -302,8 +313,7 @@ __global__ void __launch_bounds__(256) k_sweep_yz(SweepParams p, const DevGrid* 
           }
         }
         if (act[0])
-          store_group<T, LAY, COLS>(dst, q0 + (int64_t)(j + 2) * stride, ptot, lane, out,
-                                    act[COLS - 1]);
+          store_group<T, LAY, COLS>(dst, q0 + (int64_t)(j + 2) * stride, ptot, lane, out, act);
         if (FUSE) {
 #pragma unroll
           for (int m = 0; m < COLS; ++m) {
@@ -341,8 +351,9 @@ __global__ void __launch_bounds__(256) k_sweep_yz(SweepParams p, const DevGrid* 
 // XM_ROWS.  Tile = (R whole x rows at consecutive z) x (segment of p.seg
 // rows along y).  A row takes P lanes: one per cell (P = n0), or, when an x
 // face is linked to a sub-block, one per padded position x = -2 .. n0+1
-// (P = n0 + 4) so that the four ghost lanes load the padding the halo copy
-// filled.  Otherwise the lanes holding cells 0, 1, n0-2, n0-1 also write the
+// (P = n0 + 4) so that the four ghost lanes load the cells beyond the faces
+// (a linked face's from the neighbouring sub-block).  Otherwise the lanes
+// holding cells 0, 1, n0-2, n0-1 also write the
 // ghost slots the boundary condition defines (wrap or clamp).  Per loaded
 // row: publish the cells to LDS; reconstruct and publish each cell's right
 // evolved state; compute each cell's left face flux and publish it; update.
@@ -353,7 +364,8 @@ __global__ void __launch_bounds__(256) k_sweep_yz(SweepParams p, const DevGrid* 
 // and a y segment; its 64 lanes hold the positions x = x0-2 .. x0+61, and
 // the four outside the strip (ghost lanes) load the cells their positions
 // name: the neighbouring strips' cells inside the row, at its ends what the
-// face names (clamped, wrapped or padding).  Neighbours are read by whole-wave
+// face names (clamped or wrapped, or the linked sub-block's cells).
+// Neighbours are read by whole-wave
 // lane shifts, so waves are independent (no LDS, no barriers) and a row may
 // have any length; every lane runs the whole x sweep and the strip's cells
 // take exactly the arithmetic of an unbroken row.  The workgroup's waves take
@@ -361,9 +373,10 @@ __global__ void __launch_bounds__(256) k_sweep_yz(SweepParams p, const DevGrid* 
 //
 // Rows outside the grid along y are the mapped interior rows (periodic,
 // transmissive) or the padding rows of a linked face, which hold the
-// neighbour's state before this pass (and, at their x ends, the diagonal
-// neighbour's: the x halo copy that precedes this pass covers the y padding
-// rows); the pass x-sweeps them like any other row.
+// neighbour's state before this pass (the y halo copy fills them); at their
+// x ends a linked x face's lanes read the x neighbour's own y padding rows,
+// which hold the diagonal neighbour's cells.  The pass x-sweeps them like
+// any other row.
 //
 // Rings: raw rows are loaded PF iterations before they are x-swept (PF = 3
 // in the rows form, 1 in the wave strips); x-swept rows j, j+1, j+2 are
@@ -422,7 +435,7 @@ template <typename T, int XM> constexpr int xy_prefetch() {
 // strips only): also reduce |u_d| + c of the new states into the group's
 // wave-speed slots, for grids one cell thick in z, where this pass is the
 // whole step.
-template <typename T, int LAY, int XM, bool FUSE>
+template <typename T, int LAY, int XM, bool FUSE, bool LINKX>
 __global__ void __launch_bounds__(XM == XM_WAVES ? XY_WAVE_THREADS : XY_THREADS)
     __attribute__((amdgpu_waves_per_eu(XM == XM_WAVES && !FUSE ? xy_wave_occupancy<T>() : 1)))
     k_sweep_xy(SweepParams p, const DevGrid* __restrict__ grids,
@@ -499,6 +512,51 @@ __global__ void __launch_bounds__(XM == XM_WAVES ? XY_WAVE_THREADS : XY_THREADS)
 
     auto row = [&](int j) -> int64_t {
       return q0 + (int64_t)(face_index(min(j, jlast), ny, mlo, mhi) + 2) * G.px;
+    };
+
+    // Lanes past an x face linked to a sub-block read that neighbour's cells
+    // (the state this pass starts from) instead of this grid's padding, so no
+    // x halo copy precedes the pass.  Outside the y interior they read the
+    // neighbour's y padding rows, which the y halo copy before the pass
+    // filled from the diagonal neighbour (the corner cells).  The lanes load
+    // this grid's padding first (in bounds, unused) and the neighbour's cells
+    // over it.
+    struct Nbr {
+      const void* src;
+      int64_t base, px, ptot;
+      uint32_t lane;
+      int mlo, mhi;
+      bool mine, any;
+    };
+    auto nbr_source = [&](int side) {
+      Nbr r{};
+      if (!LINKX || G.mode[side] != FACE_HALO) return r;
+      const DevGrid& N = grids[uniform(G.nbr_x[side])];
+      r.mine = row_on && (side == 0 ? x < 0 : xq >= nx);
+      const int xn = r.mine ? (side == 0 ? N.n[0] + x : xq - nx) : 0;
+      r.src = N.buf[p.in];
+      r.px = N.px;
+      r.ptot = N.ptot;
+      r.mlo = N.mode[2];
+      r.mhi = N.mode[3];
+      r.base = uniform(((int64_t)(kb + 2) * N.pxy + N.ox) & ~int64_t(63));
+      r.lane = Layout<LAY>::rel((uint32_t)((int64_t)(kc + 2) * N.pxy + xn + N.ox - r.base)) *
+               (uint32_t)sizeof(T);
+      r.any = __any(r.mine);
+      return r;
+    };
+    const Nbr nlo = nbr_source(0), nhi = nbr_source(1);
+    auto load_row = [&](int j, T out[5]) __attribute__((always_inline)) {
+      load_cell_rel<T, LAY>(src, row(j), ptot, lane, out);
+      if constexpr (!LINKX) return;
+      if (nlo.any && nlo.mine)
+        load_cell_rel<T, LAY>(nlo.src, nlo.base + (int64_t)(face_index(min(j, jlast), ny, nlo.mlo,
+                                                                       nlo.mhi) + 2) * nlo.px,
+                              nlo.ptot, nlo.lane, out);
+      if (nhi.any && nhi.mine)
+        load_cell_rel<T, LAY>(nhi.src, nhi.base + (int64_t)(face_index(min(j, jlast), ny, nhi.mlo,
+                                                                       nhi.mhi) + 2) * nhi.px,
+                              nhi.ptot, nhi.lane, out);
     };
 
     // x sweep of one row held by the lanes: u (this lane's cell) -> o
@@ -632,11 +690,11 @@ __global__ void __launch_bounds__(XM == XM_WAVES ? XY_WAVE_THREADS : XY_THREADS)
     T smax[3] = {T(0), T(0), T(0)};
     bool bad = false;
 #pragma unroll
-    for (int k = 0; k < PF; ++k) load_cell_rel<T, LAY>(src, row(j0 - 2 + k), ptot, lane, raw[k]);
+    for (int k = 0; k < PF; ++k) load_row(j0 - 2 + k, raw[k]);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       xsweep(raw[i % PF], xs[i % 3]);                               // rows j0-2 .. j0+1
-      load_cell_rel<T, LAY>(src, row(j0 - 2 + i + PF), ptot, lane, raw[i % PF]);
+      load_row(j0 - 2 + i + PF, raw[i % PF]);
       if (i == 2) {
 #pragma unroll
         for (int c = 0; c < 5; ++c) {
@@ -672,7 +730,7 @@ __global__ void __launch_bounds__(XM == XM_WAVES ? XY_WAVE_THREADS : XY_THREADS)
         if (o >= len) break;
         const int j = j0 + o;
         xsweep(raw[(k + 4) % PF], xs[(k + 1) % 3]);                // row j + 2
-        load_cell_rel<T, LAY>(src, row(j + 2 + PF), ptot, lane, raw[(k + 4) % PF]);
+        load_row(j + 2 + PF, raw[(k + 4) % PF]);
         const T* uj = xs[(k + 2) % 3];
         const T* uj1 = xs[k % 3];
         const T* uj2 = xs[(k + 1) % 3];
@@ -820,7 +878,11 @@ __global__ void __launch_bounds__(256) k_halo(Work w, int buf, int axis, int ext
   const int d_o0 = a0 == 0 ? Gd.ox : 2, s_o0 = a0 == 0 ? Gs.ox : 2;
   for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < 2 * area;
        e += gridDim.x * blockDim.x) {
-    const uint32_t layer = e / area, r = e - layer * area;
+    // x faces: the two layers are adjacent cells of one row, so neighbouring
+    // lanes take the two layers of a row (one 64-byte sector per component
+    // and row, fetched once); y and z faces: lanes run along x rows
+    const uint32_t layer = axis == 0 ? (e & 1u) : e / area;
+    const uint32_t r = axis == 0 ? (e >> 1) : e - layer * area;
     const int ia = (int)(r % na) - ext;
     const uint32_t ib = r / na;
     // index along the axis: destination padding, source interior edge
@@ -1136,6 +1198,8 @@ static hipError_t sweep_typed(int axis, const Tiling& tl, const SweepParams& p, 
     // FP64 runs one cell per thread only (see sweep_xy_typed)
     if constexpr (sizeof(T) == 4) {
       if (tl.yz_cols == 2) return sweep_yz_cols<T, LAY, 2>(axis, tl, p, blocks, s);
+      if constexpr (LAY != LAY_AOS)
+        if (tl.yz_cols == 4) return sweep_yz_cols<T, LAY, 4>(axis, tl, p, blocks, s);
     }
     return sweep_yz_cols<T, LAY, 1>(axis, tl, p, blocks, s);
   }
@@ -1161,18 +1225,26 @@ hipError_t launch_sweep(int dtype, int lay, int axis, const Tiling& tl, const Sw
                                 : sweep_lay<double>(lay, axis, tl, p, grid_blocks, s);
 }
 
+template <typename T, int LAY, bool LINKX>
+static hipError_t sweep_xy_linked(const SweepParams& p, int blocks, hipStream_t s) {
+  if (p.xmode == XM_WAVES && p.fuse_s)
+    hipLaunchKernelGGL((k_sweep_xy<T, LAY, XM_WAVES, true, LINKX>), dim3(blocks),
+                       dim3(XY_WAVE_THREADS), 0, s, p, p.w.grids, p.tiles.tile_start, p.w.lam);
+  else if (p.xmode == XM_WAVES)
+    hipLaunchKernelGGL((k_sweep_xy<T, LAY, XM_WAVES, false, LINKX>), dim3(blocks),
+                       dim3(XY_WAVE_THREADS), 0, s, p, p.w.grids, p.tiles.tile_start, p.w.lam);
+  else
+    hipLaunchKernelGGL((k_sweep_xy<T, LAY, XM_ROWS, false, LINKX>), dim3(blocks), dim3(XY_THREADS),
+                       0, s, p, p.w.grids, p.tiles.tile_start, p.w.lam);
+  return hipGetLastError();
+}
+
+// Batches with an x face linked to a sub-block run the variant whose lanes
+// past such a face read the neighbour's cells; the others carry no code for it.
 template <typename T, int LAY>
 static hipError_t sweep_xy_typed(const Tiling&, const SweepParams& p, int blocks, hipStream_t s) {
-  if (p.xmode == XM_WAVES && p.fuse_s)
-    hipLaunchKernelGGL((k_sweep_xy<T, LAY, XM_WAVES, true>), dim3(blocks), dim3(XY_WAVE_THREADS), 0,
-                       s, p, p.w.grids, p.tiles.tile_start, p.w.lam);
-  else if (p.xmode == XM_WAVES)
-    hipLaunchKernelGGL((k_sweep_xy<T, LAY, XM_WAVES, false>), dim3(blocks), dim3(XY_WAVE_THREADS), 0,
-                       s, p, p.w.grids, p.tiles.tile_start, p.w.lam);
-  else
-    hipLaunchKernelGGL((k_sweep_xy<T, LAY, XM_ROWS, false>), dim3(blocks), dim3(XY_THREADS), 0, s,
-                       p, p.w.grids, p.tiles.tile_start, p.w.lam);
-  return hipGetLastError();
+  return p.link_x ? sweep_xy_linked<T, LAY, true>(p, blocks, s)
+                  : sweep_xy_linked<T, LAY, false>(p, blocks, s);
 }
 
 template <typename T>
@@ -1241,6 +1313,44 @@ hipError_t launch_halo(int dtype, int lay, const Work& w, int buf, int axis, int
   const dim3 grid((unsigned)bx, (unsigned)ntasks);
   return dtype == RIPPLE_FV_F32 ? halo_lay<float>(lay, w, buf, axis, ext, tasks, grid, s)
                                 : halo_lay<double>(lay, w, buf, axis, ext, tasks, grid, s);
+}
+
+// Plain device copy, the reference stream for HBM bandwidth: every byte read
+// once and written once in 16-byte accesses, four per thread, consecutive
+// lanes on consecutive addresses.  NT: the stores carry the non-temporal hint.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+template <bool NT>
+__global__ void __launch_bounds__(256) k_stream_copy(const u32x4* __restrict__ src,
+                                                     u32x4* __restrict__ dst, int64_t n16) {
+  const int64_t base = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+  u32x4 v[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int64_t i = base + k * 256;
+    if (i < n16) v[k] = src[i];
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int64_t i = base + k * 256;
+    if (i < n16) {
+      if constexpr (NT) __builtin_nontemporal_store(v[k], &dst[i]);
+      else dst[i] = v[k];
+    }
+  }
+}
+
+hipError_t launch_stream_copy(void* dst, const void* src, int64_t bytes, int nt, hipStream_t s) {
+  const int64_t n16 = bytes / 16;
+  if (n16 <= 0) return hipSuccess;
+  const int64_t blocks = (n16 + 1023) / 1024;
+  if (nt)
+    hipLaunchKernelGGL(k_stream_copy<true>, dim3((unsigned)blocks), dim3(256), 0, s,
+                       static_cast<const u32x4*>(src), static_cast<u32x4*>(dst), n16);
+  else
+    hipLaunchKernelGGL(k_stream_copy<false>, dim3((unsigned)blocks), dim3(256), 0, s,
+                       static_cast<const u32x4*>(src), static_cast<u32x4*>(dst), n16);
+  return hipGetLastError();
 }
 
 static unsigned fill_blocks(int64_t n) {

@@ -55,6 +55,15 @@ template <> struct Layout<LAY_AOSOA64> : LayoutBlocked<6> {};
 // host bounds grid shapes accordingly).
 constexpr int BUFFER_DWORD3 = 0x00020000;  // raw buffer, gfx9-family format word
 constexpr int BUFFER_RECORDS = 0x7fffffff;
+// Cache-policy bits of the hot-path loads and stores (0: the default policy).
+#ifndef RFV_LOAD_POLICY
+#define RFV_LOAD_POLICY 0
+#endif
+#ifndef RFV_STORE_POLICY
+#define RFV_STORE_POLICY 0
+#endif
+constexpr int LD_POL = RFV_LOAD_POLICY;
+constexpr int ST_POL = RFV_STORE_POLICY;
 
 // Values that are the same in every lane, stated as such so the compiler keeps
 // them in scalar registers (without this it may treat a tile's grid index as
@@ -76,19 +85,19 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void* base) {
 template <typename T>
 __device__ __forceinline__ T gload(const void* base, uint32_t lane_bytes) {
   if constexpr (sizeof(T) == 4) {
-    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rsrc(base), (int)lane_bytes, 0, 0));
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rsrc(base), (int)lane_bytes, 0, LD_POL));
   } else {
-    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rsrc(base), (int)lane_bytes, 0, 0));
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rsrc(base), (int)lane_bytes, 0, LD_POL));
   }
 }
 
 template <typename T>
 __device__ __forceinline__ void gstore(void* base, uint32_t lane_bytes, T v) {
   if constexpr (sizeof(T) == 4) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), rsrc(base), (int)lane_bytes, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), rsrc(base), (int)lane_bytes, 0, ST_POL);
   } else {
     using u2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(rsrc(base), 0, 0, 0));
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), rsrc(base), (int)lane_bytes, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), rsrc(base), (int)lane_bytes, 0, ST_POL);
   }
 }
 
@@ -99,13 +108,13 @@ __device__ __forceinline__ void gload_n(const void* base, uint32_t lane_bytes, T
   constexpr int B = (int)sizeof(T) * N;
   static_assert(B == 4 || B == 8 || B == 16, "unsupported access width");
   if constexpr (B == 4) {
-    const uint32_t v = __builtin_amdgcn_raw_buffer_load_b32(rsrc(base), (int)lane_bytes, 0, 0);
+    const uint32_t v = __builtin_amdgcn_raw_buffer_load_b32(rsrc(base), (int)lane_bytes, 0, LD_POL);
     __builtin_memcpy(out, &v, B);
   } else if constexpr (B == 8) {
-    const auto v = __builtin_amdgcn_raw_buffer_load_b64(rsrc(base), (int)lane_bytes, 0, 0);
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(rsrc(base), (int)lane_bytes, 0, LD_POL);
     __builtin_memcpy(out, &v, B);
   } else {
-    const auto v = __builtin_amdgcn_raw_buffer_load_b128(rsrc(base), (int)lane_bytes, 0, 0);
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(rsrc(base), (int)lane_bytes, 0, LD_POL);
     __builtin_memcpy(out, &v, B);
   }
 }
@@ -117,15 +126,15 @@ __device__ __forceinline__ void gstore_n(void* base, uint32_t lane_bytes, const 
   if constexpr (B == 4) {
     uint32_t v;
     __builtin_memcpy(&v, in, B);
-    __builtin_amdgcn_raw_buffer_store_b32(v, rsrc(base), (int)lane_bytes, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(v, rsrc(base), (int)lane_bytes, 0, ST_POL);
   } else if constexpr (B == 8) {
     decltype(__builtin_amdgcn_raw_buffer_load_b64(rsrc(base), 0, 0, 0)) v;
     __builtin_memcpy(&v, in, B);
-    __builtin_amdgcn_raw_buffer_store_b64(v, rsrc(base), (int)lane_bytes, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(v, rsrc(base), (int)lane_bytes, 0, ST_POL);
   } else {
     decltype(__builtin_amdgcn_raw_buffer_load_b128(rsrc(base), 0, 0, 0)) v;
     __builtin_memcpy(&v, in, B);
-    __builtin_amdgcn_raw_buffer_store_b128(v, rsrc(base), (int)lane_bytes, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(v, rsrc(base), (int)lane_bytes, 0, ST_POL);
   }
 }
 
@@ -150,7 +159,7 @@ __device__ __forceinline__ void store_cell_rel(void* buf, int64_t q0, int64_t pt
     gstore<T>(const_cast<void*>(comp_base<T, LAY>(buf, q0, c, ptot)), lane_bytes, u[c]);
 }
 
-// COLS consecutive cells along x starting at an even cell q0 + r (r even):
+// COLS consecutive cells along x starting at cell q0 + r, r a multiple of COLS:
 // u[k][c] is component c of cell k.  In SoA and AoSoA the COLS values of one
 // component are adjacent in memory and move as one wider access; in AoS each
 // cell is read on its own.
@@ -174,22 +183,22 @@ __device__ __forceinline__ void load_group(const void* buf, int64_t q0, int64_t 
   }
 }
 
-// Store of a group; `all` says every cell of the group is written, otherwise
-// only cell 0 (the group that straddles the end of an odd-length row).
+// Store of a group: act[k] says whether cell k lies inside the row.  A
+// whole group moves as one wider access per component (SoA, AoSoA); the
+// group that straddles the end of a row stores its cells one by one.
 template <typename T, int LAY, int COLS>
 __device__ __forceinline__ void store_group(void* buf, int64_t q0, int64_t ptot,
-                                            uint32_t lane_bytes, const T u[COLS][5], bool all) {
+                                            uint32_t lane_bytes, const T u[COLS][5],
+                                            const bool act[COLS]) {
   if constexpr (COLS == 1) {
     store_cell_rel<T, LAY>(buf, q0, ptot, lane_bytes, u[0]);
   } else if constexpr (LAY == LAY_AOS) {
-    store_cell_rel<T, LAY>(buf, q0, ptot, lane_bytes, u[0]);
-    if (all) {
 #pragma unroll
-      for (int k = 1; k < COLS; ++k)
+    for (int k = 0; k < COLS; ++k)
+      if (act[k])
         store_cell_rel<T, LAY>(buf, q0, ptot, lane_bytes + (uint32_t)(5 * k * sizeof(T)), u[k]);
-    }
   } else {
-    if (all) {
+    if (act[COLS - 1]) {
 #pragma unroll
       for (int c = 0; c < 5; ++c) {
         T v[COLS];
@@ -198,7 +207,10 @@ __device__ __forceinline__ void store_group(void* buf, int64_t q0, int64_t ptot,
         gstore_n<T, COLS>(const_cast<void*>(comp_base<T, LAY>(buf, q0, c, ptot)), lane_bytes, v);
       }
     } else {
-      store_cell_rel<T, LAY>(buf, q0, ptot, lane_bytes, u[0]);
+#pragma unroll
+      for (int k = 0; k < COLS - 1; ++k)
+        if (act[k])
+          store_cell_rel<T, LAY>(buf, q0, ptot, lane_bytes + (uint32_t)(k * sizeof(T)), u[k]);
     }
   }
 }

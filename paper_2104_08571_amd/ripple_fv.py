@@ -22,6 +22,7 @@ F32, F64 = 0, 1
 TRANSMISSIVE, PERIODIC = 0, 1
 PRIMITIVE, CONSERVED = 0, 1
 RUN_EAGER, RUN_GRAPH, RUN_PER_GRID, RUN_PROFILE = 0, 1, 2, 4
+COPY_NONTEMPORAL = 1
 K_WAVESPEED, K_DT, K_SWEEP_X, K_SWEEP_Y, K_SWEEP_Z, K_HALO, K_SWEEP_XY, NKERNELS = range(8)
 KERNEL_NAMES = ["wavespeed", "dt", "sweep_x", "sweep_y", "sweep_z", "halo", "sweep_xy"]
 AXIS_XY = 3
@@ -31,9 +32,11 @@ NVAR = 5
 EXPORTED = [
     "ripple_fv_grid_init", "ripple_fv_create", "ripple_fv_destroy", "ripple_fv_import",
     "ripple_fv_export", "ripple_fv_convert", "ripple_fv_max_wavespeed", "ripple_fv_sweep",
-    "ripple_fv_step", "ripple_fv_run_batch", "ripple_fv_batch_time", "ripple_fv_batch_tune",
+    "ripple_fv_step", "ripple_fv_run_batch",
+    "ripple_fv_batch_time", "ripple_fv_batch_tune",
     "ripple_fv_partition", "ripple_fv_halo_exchange", "ripple_fv_conserved_sums",
-    "ripple_fv_error_norms", "ripple_fv_check", "ripple_fv_profile", "ripple_fv_status_string",
+    "ripple_fv_error_norms", "ripple_fv_stream_copy", "ripple_fv_check", "ripple_fv_profile",
+    "ripple_fv_status_string",
     "ripple_fv_last_error",
     "ripple_force2d_grid_init", "ripple_force2d_import", "ripple_force2d_export",
     "ripple_force2d_flux_difference",
@@ -164,6 +167,7 @@ def _declare(L):
                                          ctypes.c_int32, vp]),
         "ripple_fv_conserved_sums": (st, [vp, gp, vp, vp, vp]),
         "ripple_fv_error_norms": (st, [vp, gp, vp, vp, vp, vp, vp]),
+        "ripple_fv_stream_copy": (st, [vp, vp, vp, ctypes.c_int64, ctypes.c_int32, vp]),
         "ripple_fv_check": (st, [vp]),
         "ripple_fv_profile": (st, [vp, dp, ctypes.POINTER(ctypes.c_int64)]),
         "ripple_fv_status_string": (ctypes.c_char_p, [st]),
@@ -290,6 +294,10 @@ def ripple_fv_conserved_sums(ctx, g, u, sums_dev, stream=None):
 def ripple_fv_error_norms(ctx, g, u, ref_dev, l1_dev, linf_dev, stream=None):
     _check(lib().ripple_fv_error_norms(ctx, ctypes.byref(g), u, ref_dev, l1_dev, linf_dev, stream),
            ctx)
+
+
+def ripple_fv_stream_copy(ctx, dst, src, nbytes, flags=0, stream=None):
+    _check(lib().ripple_fv_stream_copy(ctx, dst, src, int(nbytes), int(flags), stream), ctx)
 
 
 def ripple_fv_check(ctx):

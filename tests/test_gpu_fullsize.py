@@ -284,14 +284,27 @@ def test_partition_768_fp32_100_steps(request):
         assert np.array_equal(U, part), o
     del parts
     # mirror symmetry on bands through the centre (x and y mirrors on a band of
-    # z planes, the z mirror on a band of y rows)
-    scale = np.abs(ref[:, 380:388]).max(axis=(1, 2, 3), keepdims=True)
+    # z planes, the z mirror on a band of y rows).  In FP32 a cell and its
+    # mirror image round differently (the sweeps run in one direction), so
+    # the two halves agree to within the FP32 path's error against the
+    # symmetric FP64 solution: twice the elementwise parity bound, relative
+    # to each variable's scale in the band (momenta: the largest of the three)
+    def asym(M, band):
+        mx = np.abs(band).max(axis=(1, 2, 3))
+        scale = np.array([mx[0]] + [mx[1:4].max()] * 3 + [mx[4]])
+        return np.abs(M - band).max(axis=(1, 2, 3)) / scale
+
+    bound = 2 * G.LINF_FACTOR * TOL[R.F32]
     band = ref[:, 372:396]
     for axis in (2, 3):
         M = np.flip(band, axis=axis).copy()
         M[4 - axis] *= -1
-        assert (np.abs(M - band) <= 1e-5 * scale).all(), axis
+        a = asym(M, band)
+        say(request, f"768^3 after 100 steps: mirror asymmetry, axis {4 - axis}: {a}")
+        assert (a <= bound).all(), (axis, a)
     band = ref[:, :, 372:396]
     M = np.flip(band, axis=1).copy()
     M[3] *= -1
-    assert (np.abs(M - band) <= 1e-5 * scale).all()
+    a = asym(M, band)
+    say(request, f"768^3 after 100 steps: mirror asymmetry, axis z: {a}")
+    assert (a <= bound).all(), a

@@ -54,22 +54,23 @@ def test_tiling_invariance_bitwise(dtype):
                          ids=["soa", "aosoa32", "aos"])
 @pytest.mark.parametrize("split", [1, 0], ids=["separate", "fused"])
 def test_yz_columns_per_thread_bitwise(layout, w, split):
-    """FP32 y and z sweeps advancing one or two adjacent x cells per thread
-    (the two-cell groups move each component as one 8-byte access) give the
-    same bits, on rows of odd and even length, with the separate and the
+    """FP32 y and z sweeps advancing one, two or four adjacent x cells per
+    thread (a group moves each component as one 8- or 16-byte access; AoS
+    runs two for four) give the same bits, on rows whose length is and is not
+    a multiple of the group, with the separate and the
     fused x-y pass; the lane shifts of the wave-strip form (whose end lanes
     receive zero) against the rows form are covered by test_gpu_fused."""
     for shape, bc in (((37, 29, 23), (1, 0, 1)), ((64, 18, 40), (0, 1, 1)), ((17, 33, 9), (1, 1, 0))):
         W = smooth(shape, seed=13)
         outs = []
-        for cols in (1, 2):
+        for cols in (1, 2, 4):
             g = R.make_grid(shape, dtype=R.F32, layout=layout, aosoa_w=w, bc=bc,
                             tiling=(0, 0, 0, 0, cols, split))
             outs.append(G.run(g, W, 3))
         (U1,), (t1,) = outs[0]
-        (U2,), (t2,) = outs[1]
-        assert t1 == t2, (shape, cols)
-        assert np.array_equal(U1, U2), (shape, layout, split)
+        for cols, ((U,), (t,)) in zip((2, 4), outs[1:]):
+            assert t == t1, (shape, cols)
+            assert np.array_equal(U, U1), (shape, layout, split, cols)
 
 
 def _batch(dtype, layout=R.SOA, aosoa_w=0):

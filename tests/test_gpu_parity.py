@@ -130,21 +130,19 @@ def test_conserved_sums_and_norms():
     scale = np.abs(U).reshape(5, -1).sum(1)
     assert (np.abs(sums.cpu().numpy() - U.reshape(5, -1).sum(1)) <= 1e-13 * scale).all()
     r = ref.cpu().numpy()
-    l1, linf = l1.cpu().numpy(), linf.cpu().numpy()
+    e1, einf = l1.cpu().numpy(), linf.cpu().numpy()
     for c in range(5):
-        np.testing.assert_allclose(l1[c], np.abs(U[c] - r[c]).sum() / np.abs(r[c]).sum(),
+        np.testing.assert_allclose(e1[c], np.abs(U[c] - r[c]).sum() / np.abs(r[c]).sum(),
                                    rtol=1e-12)
         # maxima are exact, so the ratio is one correctly rounded division
-        assert linf[c] == np.abs(U[c] - r[c]).max() / np.abs(r[c]).max()
+        assert einf[c] == np.abs(U[c] - r[c]).max() / np.abs(r[c]).max()
     # a vanishing reference: 0 where the state matches it, else +inf
     zero = torch.zeros_like(ref)
     R.ripple_fv_error_norms(G.ctx(), g, buf.data_ptr(), zero.data_ptr(), l1.data_ptr(),
                             linf.data_ptr(), G.stream())
     torch.cuda.synchronize()
-    l1, linf = l1.cpu().numpy(), linf.cpu().numpy()
-    assert np.isinf(l1).all() and np.isinf(linf).all()
-    Z = G.buffer(g)
-    Zs = G.load(g, np.zeros_like(U), Z, variables=R.CONSERVED)
+    assert np.isinf(l1.cpu().numpy()).all() and np.isinf(linf.cpu().numpy()).all()
+    Zs = G.load(g, np.zeros_like(U), variables=R.CONSERVED)
     R.ripple_fv_error_norms(G.ctx(), g, Zs.data_ptr(), zero.data_ptr(), l1.data_ptr(),
                             linf.data_ptr(), G.stream())
     torch.cuda.synchronize()
@@ -176,3 +174,20 @@ def test_nonphysical_flag_and_recovery():
     R.ripple_fv_run_batch(G.ctx(), [g], [a.data_ptr()], [b.data_ptr()], 1, 0.9, 0, G.stream())
     assert R.ripple_fv_check(G.ctx()) == R.E_NONPHYSICAL
     assert R.ripple_fv_check(G.ctx()) == R.OK  # cleared by the first check
+
+
+def test_stream_copy():
+    """The reference copy moves every byte, in both store policies, and
+    rejects sizes that are not a multiple of 16 and overlapping ranges."""
+    n = (1 << 20) + 48
+    src = torch.randint(0, 255, (n,), dtype=torch.uint8, device="cuda")
+    for flags in (0, R.COPY_NONTEMPORAL):
+        dst = torch.zeros_like(src)
+        R.ripple_fv_stream_copy(G.ctx(), dst.data_ptr(), src.data_ptr(), n, flags, G.stream())
+        torch.cuda.synchronize()
+        assert torch.equal(dst, src)
+    s = G.stream()
+    assert R.call("ripple_fv_stream_copy", G.ctx(), dst.data_ptr(), src.data_ptr(), 24, 0, s) == R.E_INVALID
+    assert R.call("ripple_fv_stream_copy", G.ctx(), src.data_ptr() + 16, src.data_ptr(), 1024, 0, s) == R.E_INVALID
+    assert R.call("ripple_fv_stream_copy", G.ctx(), dst.data_ptr(), src.data_ptr(), 1024, 2, s) == R.E_INVALID
+    assert R.ripple_fv_check(G.ctx()) == R.OK
