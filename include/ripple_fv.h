@@ -271,6 +271,31 @@ ripple_fv_status ripple_fv_run_batch(ripple_fv_ctx* ctx, int32_t n, const ripple
                                      void* const* u, void* const* work, int32_t nsteps,
                                      double cfl, int32_t flags, void* stream);
 
+/* ripple_fv_run_batch for callers that cannot allocate: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  It
+ * advances n grids by nsteps steps exactly as ripple_fv_run_batch with
+ * RIPPLE_FV_RUN_EAGER does (same kernels, same results bit for bit, the state
+ * in place in u[i], work[i] clobbered), but calls no hipMalloc, hipFree or
+ * other allocating routine: the batch's descriptors, tile lists, halo copy
+ * tasks and per-grid dt / wave-speed slots live in a file-scope device array
+ * of RIPPLE_FV_NOALLOC_SCRATCH_BYTES bytes (32 KiB), which each device the
+ * library runs on holds until the process ends.  Each call first writes the
+ * whole workspace it uses (zeroed slots included) by small copy kernels that
+ * carry the bytes in their arguments, then enqueues the steps on `stream`.
+ * Limit: n <= RIPPLE_FV_NOALLOC_MAX_GRIDS (64); more grids give E_INVALID
+ * with nothing enqueued.  Every call on one device shares that device's
+ * array and leaves its contents behind: calls that overlap on one device
+ * (on different streams, or from different contexts) race; calls in the
+ * order of one stream do not.  The time reached is not reported
+ * (ripple_fv_batch_time covers ripple_fv_run_batch only); the non-physical
+ * flag is the context's, read by ripple_fv_check. */
+#define RIPPLE_FV_NOALLOC_MAX_GRIDS 64
+#define RIPPLE_FV_NOALLOC_SCRATCH_BYTES 32768
+ripple_fv_status ripple_fv_run_batch_noalloc(ripple_fv_ctx* ctx, int32_t n,
+                                             const ripple_fv_grid* grids, void* const* u,
+                                             void* const* work, int32_t nsteps, double cfl,
+                                             void* stream);
+
 /* Time reached (t_host[i], since the start of the last ripple_fv_run_batch
  * call on this grid set) and the last dt per grid (dt_host, may be NULL).
  * Synchronises the device. */

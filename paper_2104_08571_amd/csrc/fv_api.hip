@@ -11,6 +11,7 @@
 #include <deque>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -19,6 +20,9 @@
 
 using namespace rfv;
 
+// The scratch array of ripple_fv_run_batch_noalloc (see scratch_address).
+static __device__ __align__(256) unsigned char scratch[RIPPLE_FV_NOALLOC_SCRATCH_BYTES];
+
 namespace {
 
 constexpr int64_t MAX_BYTES = int64_t(1) << 46;
@@ -26,9 +30,36 @@ constexpr int MAX_PLANS = 16;
 constexpr int GRAPH_MAX_STEPS = 64;  // steps captured in one graph
 constexpr int MAX_GRAPHS = 4;        // cached graphs per plan
 
-// Launch description of a batch over storage owned elsewhere (a cached Plan
-// owns heap vectors and one device allocation; other storage can back the
-// same view).  The enqueue functions read only this.
+// Workspace of ripple_fv_run_batch_noalloc: a file-scope device array, one
+// copy per device, held until the process ends.  In host code its name is a
+// host-side stand-in, not a device address; the device address comes from
+// hipGetSymbolAddress, taken once per device (scratch_address) with that
+// device current, and only that address is handed to kernels and copies.
+constexpr int NOALLOC_MAX_GRIDS = RIPPLE_FV_NOALLOC_MAX_GRIDS;
+constexpr size_t SCRATCH_BYTES = RIPPLE_FV_NOALLOC_SCRATCH_BYTES;
+
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+unsigned char* scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of `device`'s scratch array (the device must be current).
+hipError_t scratch_address(int device, unsigned char** out) {
+  if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    scratch_ptr[device] = static_cast<unsigned char*>(p);
+  }
+  *out = scratch_ptr[device];
+  return hipSuccess;
+}
+
+// Launch description of a batch over storage owned elsewhere: by a cached
+// Plan (heap vectors and one device allocation) or, in the allocation-free
+// entry point, by stack arrays and the device scratch array.  The enqueue
+// functions read only this.
 struct PlanCore {
   int n = 0;
   int dtype = 0, lay = 0;
@@ -156,6 +187,7 @@ struct ripple_fv_ctx {
   double prof_ms[RIPPLE_FV_NKERNELS] = {0};
   int64_t prof_n[RIPPLE_FV_NKERNELS] = {0};
   std::map<std::string, std::vector<ripple_fv_grid>> tune_cache;
+  unsigned char* scratch = nullptr; // device address of this device's scratch array
 };
 
 namespace {
@@ -914,6 +946,10 @@ ripple_fv_status ripple_fv_create(ripple_fv_ctx** out, int32_t device) {
     return RIPPLE_FV_E_NOMEM;
   if (hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess)
     return RIPPLE_FV_E_DEVICE;
+  if (scratch_address(device, &ctx->scratch) != hipSuccess) {
+    (void)hipGetLastError();
+    return RIPPLE_FV_E_DEVICE;
+  }
   *out = ctx.release();
   return RIPPLE_FV_OK;
 }
@@ -1051,6 +1087,57 @@ ripple_fv_status ripple_fv_run_batch(ripple_fv_ctx* ctx, int32_t n, const ripple
   ripple_fv_status st = set_device(ctx);
   if (st) return st;
   return run(ctx, n, grids, u, work, nsteps, cfl, 0.0, nullptr, flags, (hipStream_t)stream);
+}
+
+ripple_fv_status ripple_fv_run_batch_noalloc(ripple_fv_ctx* ctx, int32_t n,
+                                             const ripple_fv_grid* grids, void* const* u,
+                                             void* const* work, int32_t nsteps, double cfl,
+                                             void* stream) {
+  ripple_fv_status st = set_device(ctx);
+  if (st) return st;
+  if (n > NOALLOC_MAX_GRIDS)
+    return fail(ctx, RIPPLE_FV_E_INVALID,
+                "ripple_fv_run_batch_noalloc: more than RIPPLE_FV_NOALLOC_MAX_GRIDS (64) grids");
+  if (nsteps < 0) return fail(ctx, RIPPLE_FV_E_INVALID, "nsteps < 0");
+  if (!(cfl > 0.0 && cfl <= 1.0)) return fail(ctx, RIPPLE_FV_E_INVALID, "cfl must be in (0, 1]");
+  if ((st = validate_batch(ctx, n, grids))) return st;
+  if (!u || !work) return fail(ctx, RIPPLE_FV_E_INVALID, "NULL buffer list");
+  for (int g = 0; g < n; ++g) {
+    if ((st = ptr_ok(ctx, u[g], grids[g].bytes, 256, "u"))) return st;
+    if ((st = ptr_ok(ctx, work[g], grids[g].bytes, 256, "work"))) return st;
+    if (u[g] == work[g]) return fail(ctx, RIPPLE_FV_E_INVALID, "u and work alias");
+  }
+  if (!ctx->scratch) return fail(ctx, RIPPLE_FV_E_DEVICE, "no scratch address for this device");
+  // launch shape and workspace image on the host stack
+  PlanCore P;
+  int64_t tiles[5][NOALLOC_MAX_GRIDS + 1];
+  HaloTask halo[3][2 * NOALLOC_MAX_GRIDS];
+  DevGrid hg[NOALLOC_MAX_GRIDS];
+  int64_t* tp[5] = {tiles[0], tiles[1], tiles[2], tiles[3], tiles[4]};
+  HaloTask* hp[3] = {halo[0], halo[1], halo[2]};
+  plan_shape(P, n, grids, tp, hp, hg);
+  for (int g = 0; g < n; ++g) {
+    hg[g].buf[0] = u[g];
+    hg[g].buf[1] = work[g];
+  }
+  const WsLayout L = ws_layout(n, P.nhalo);
+  if (L.total > SCRATCH_BYTES) return fail(ctx, RIPPLE_FV_E_INVALID, "workspace exceeds the scratch array");
+  alignas(16) unsigned char img[SCRATCH_BYTES];
+  std::memset(img, 0, L.total);  // dt, lambda, time and wave-speed slots start at zero
+  std::memcpy(img + L.grids, hg, sizeof(DevGrid) * n);
+  for (int k = 0; k < 5; ++k) std::memcpy(img + L.tiles[k], tiles[k], sizeof(int64_t) * (n + 1));
+  for (int k = 0; k < 3; ++k) std::memcpy(img + L.halo[k], halo[k], sizeof(HaloTask) * P.nhalo[k]);
+  ws_bind(P, reinterpret_cast<char*>(ctx->scratch), L);
+  hipStream_t s = (hipStream_t)stream;
+  HIP_OR_FAIL(ctx, launch_upload(ctx->scratch, img, L.total, s));
+  if (nsteps == 0) return RIPPLE_FV_OK;
+  Launcher Lc{ctx, s, false, {}, 0};
+  if ((st = enqueue_wavespeed(ctx, &P, Lc, 0, nullptr, false))) return st;
+  for (int k = 0; k < nsteps; ++k)
+    if ((st = enqueue_step(ctx, &P, Lc, P.in_place() ? 0 : (k & 1), cfl, 0.0, nullptr, false)))
+      return st;
+  if (!P.in_place() && (nsteps & 1)) return enqueue_copy_back(ctx, &P, s);
+  return RIPPLE_FV_OK;
 }
 
 ripple_fv_status ripple_fv_batch_time(ripple_fv_ctx* ctx, int32_t n, const ripple_fv_grid* grids,

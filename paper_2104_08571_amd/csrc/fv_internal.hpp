@@ -117,6 +117,14 @@ hipError_t launch_dt(const Work& w, double cfl, double fixed_dt, int reset_s, do
 hipError_t launch_halo(int dtype, int lay, const Work& w, int buf, int axis, int ext,
                        const HaloTask* tasks, int ntasks, int64_t max_area, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s);
+// Copy `bytes` (a multiple of 8, dst 8-byte aligned) from host memory to
+// device memory through kernel arguments, in chunks of UploadChunk::w.
+struct UploadChunk {
+  uint32_t off;        // byte offset of the chunk in the destination
+  uint32_t nwords;     // 8-byte words that follow
+  uint64_t w[240];
+};
+hipError_t launch_upload(void* dst, const void* src, size_t bytes, hipStream_t s);
 // Plain 16-byte-access device copy of `bytes` (a multiple of 16); nt: the
 // stores carry the non-temporal hint.
 hipError_t launch_stream_copy(void* dst, const void* src, int64_t bytes, int nt, hipStream_t s);

@@ -908,6 +908,14 @@ __global__ void k_fill_f64(double* p, int64_t n, double v) {
     p[i] = v;
 }
 
+// Host byte image -> device memory, carried in the kernel's arguments: the
+// copy needs no staging buffer and no allocation, and a captured launch keeps
+// its own copy of the bytes.
+__global__ void __launch_bounds__(256) k_upload(unsigned char* dst, UploadChunk c) {
+  uint64_t* d = reinterpret_cast<uint64_t*>(dst + c.off);
+  for (uint32_t i = threadIdx.x; i < c.nwords; i += blockDim.x) d[i] = c.w[i];
+}
+
 // ---------------------------------------------------------------------------
 // Transfer and diagnostic kernels (runtime layout; not on the hot path)
 // ---------------------------------------------------------------------------
@@ -1313,6 +1321,22 @@ hipError_t launch_halo(int dtype, int lay, const Work& w, int buf, int axis, int
   const dim3 grid((unsigned)bx, (unsigned)ntasks);
   return dtype == RIPPLE_FV_F32 ? halo_lay<float>(lay, w, buf, axis, ext, tasks, grid, s)
                                 : halo_lay<double>(lay, w, buf, axis, ext, tasks, grid, s);
+}
+
+hipError_t launch_upload(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  UploadChunk c;
+  const unsigned char* p = static_cast<const unsigned char*>(src);
+  for (size_t off = 0; off < bytes; off += sizeof(c.w)) {
+    const size_t len = bytes - off < sizeof(c.w) ? bytes - off : sizeof(c.w);
+    c.off = (uint32_t)off;
+    c.nwords = (uint32_t)((len + 7) / 8);
+    c.w[c.nwords - 1] = 0;
+    __builtin_memcpy(c.w, p + off, len);
+    hipLaunchKernelGGL(k_upload, dim3(1), dim3(256), 0, s, static_cast<unsigned char*>(dst), c);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 // Plain device copy, the reference stream for HBM bandwidth: every byte read

@@ -23,6 +23,8 @@ TRANSMISSIVE, PERIODIC = 0, 1
 PRIMITIVE, CONSERVED = 0, 1
 RUN_EAGER, RUN_GRAPH, RUN_PER_GRID, RUN_PROFILE = 0, 1, 2, 4
 COPY_NONTEMPORAL = 1
+NOALLOC_MAX_GRIDS = 64
+NOALLOC_SCRATCH_BYTES = 32768
 K_WAVESPEED, K_DT, K_SWEEP_X, K_SWEEP_Y, K_SWEEP_Z, K_HALO, K_SWEEP_XY, NKERNELS = range(8)
 KERNEL_NAMES = ["wavespeed", "dt", "sweep_x", "sweep_y", "sweep_z", "halo", "sweep_xy"]
 AXIS_XY = 3
@@ -32,7 +34,7 @@ NVAR = 5
 EXPORTED = [
     "ripple_fv_grid_init", "ripple_fv_create", "ripple_fv_destroy", "ripple_fv_import",
     "ripple_fv_export", "ripple_fv_convert", "ripple_fv_max_wavespeed", "ripple_fv_sweep",
-    "ripple_fv_step", "ripple_fv_run_batch",
+    "ripple_fv_step", "ripple_fv_run_batch", "ripple_fv_run_batch_noalloc",
     "ripple_fv_batch_time", "ripple_fv_batch_tune",
     "ripple_fv_partition", "ripple_fv_halo_exchange", "ripple_fv_conserved_sums",
     "ripple_fv_error_norms", "ripple_fv_stream_copy", "ripple_fv_check", "ripple_fv_profile",
@@ -160,6 +162,9 @@ def _declare(L):
         "ripple_fv_run_batch": (st, [vp, ctypes.c_int32, gp, ctypes.POINTER(vp),
                                      ctypes.POINTER(vp), ctypes.c_int32, ctypes.c_double,
                                      ctypes.c_int32, vp]),
+        "ripple_fv_run_batch_noalloc": (st, [vp, ctypes.c_int32, gp, ctypes.POINTER(vp),
+                                             ctypes.POINTER(vp), ctypes.c_int32,
+                                             ctypes.c_double, vp]),
         "ripple_fv_batch_time": (st, [vp, ctypes.c_int32, gp, dp, dp]),
         "ripple_fv_batch_tune": (st, [vp, ctypes.c_int32, gp, gp, vp]),
         "ripple_fv_partition": (st, [gp, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, gp]),
@@ -256,6 +261,12 @@ def ripple_fv_run_batch(ctx, grids, u, work, nsteps, cfl=0.9, flags=RUN_EAGER, s
     arr, n = _grids(grids)
     _check(lib().ripple_fv_run_batch(ctx, n, arr, _ptrs(u), _ptrs(work), int(nsteps),
                                      float(cfl), int(flags), stream), ctx)
+
+
+def ripple_fv_run_batch_noalloc(ctx, grids, u, work, nsteps, cfl=0.9, stream=None):
+    arr, n = _grids(grids)
+    _check(lib().ripple_fv_run_batch_noalloc(ctx, n, arr, _ptrs(u), _ptrs(work), int(nsteps),
+                                             float(cfl), stream), ctx)
 
 
 def ripple_fv_batch_time(ctx, grids):
