@@ -470,28 +470,55 @@ def run_force2d_workload(sizes, dtypes, layouts, reps, warmup):
 
 
 def copy_ceiling(nbytes=2 << 30, reps=20):
-    """Device-to-device copy rate of a plain copy kernel (torch's) over
-    `nbytes`-byte buffers: (read + write bytes) / time.  It is the practical
-    HBM ceiling that the sweeps are compared with, and the known-size program
-    against which rocprofv3's FETCH_SIZE / WRITE_SIZE counters are calibrated."""
+    """Device-to-device copy rate over `nbytes`-byte buffers, (read + write
+    bytes) / time: the library's reference copy (16-byte accesses, default and
+    non-temporal stores; median of `reps` copies timed one by one) and, for
+    comparison, the runtime's blit copy that torch's copy_ uses.  It is the
+    practical HBM ceiling the sweeps are compared with, and the known-size
+    program against which rocprofv3's FETCH_SIZE / WRITE_SIZE counters are
+    calibrated."""
     import torch
 
+    from paper_2104_08571_amd import ripple_fv as R
+
+    ctx = R.ripple_fv_create(0)
+    st = torch.cuda.current_stream()
     src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
-    for _ in range(3):
-        dst.copy_(src)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        dst.copy_(src)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    del src, dst
-    torch.cuda.empty_cache()
-    return {"bytes_per_copy": nbytes, "ms_per_copy": round(ms, 4),
-            "GBps_read_plus_write": round(2 * nbytes / (ms * 1e-3) / 1e9, 1)}
+    out = {"bytes_per_copy": nbytes}
+    try:
+        for name, flags in (("stream_copy", 0), ("stream_copy_nontemporal", R.COPY_NONTEMPORAL)):
+            for _ in range(3):
+                R.ripple_fv_stream_copy(ctx, dst.data_ptr(), src.data_ptr(), nbytes, flags,
+                                        st.cuda_stream)
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+            torch.cuda.synchronize()
+            ev[0].record(st)
+            for k in range(reps):
+                R.ripple_fv_stream_copy(ctx, dst.data_ptr(), src.data_ptr(), nbytes, flags,
+                                        st.cuda_stream)
+                ev[k + 1].record(st)
+            torch.cuda.synchronize()
+            ms = sorted(ev[k].elapsed_time(ev[k + 1]) for k in range(reps))[reps // 2]
+            out[name] = {"ms_per_copy": round(ms, 4),
+                         "GBps_read_plus_write": round(2 * nbytes / (ms * 1e-3) / 1e9, 1)}
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out["runtime_blit_copy"] = {"ms_per_copy": round(ms, 4),
+                                    "GBps_read_plus_write": round(2 * nbytes / (ms * 1e-3) / 1e9, 1)}
+    finally:
+        R.ripple_fv_destroy(ctx)
+        del src, dst
+        torch.cuda.empty_cache()
+    return out
 
 
 def cpu_baseline(n, seed, steps):
@@ -556,6 +583,8 @@ def main():
     ap.add_argument("--layout-steps", type=int, default=100)
     ap.add_argument("--layouts-only", action="store_true",
                     help="run only the 256^3 FP64 layout leg (prints its JSON)")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="run only the 64-grid batch leg (prints its JSON)")
     ap.add_argument("--no-force2d", action="store_true",
                     help="skip the 2D FORCE flux-difference leg")
     ap.add_argument("--force2d-only", action="store_true",
@@ -591,6 +620,10 @@ def main():
     pt_args = ([int(v) for v in args.particles_sizes.split(",")], args.particles_dtypes.split(","),
                args.particles_layouts.split(","), max(args.steps, 5), args.warmup)
     lay_args = (256, args.layout_steps, args.warmup, args.layouts.split(","))
+    if args.batch_only:
+        print(json.dumps({"batch_64_grids_f32": run_batch_workload(args.steps, args.warmup)}),
+              flush=True)
+        return
     if args.layouts_only:
         print(json.dumps({"layouts_256_f64": run_layout_workload(*lay_args)}), flush=True)
         return

@@ -1319,6 +1319,9 @@ struct TuneBufs {
 // median of several replays keeps one noisy timing from deciding the pick.
 constexpr int TUNE_STEPS = 4;
 constexpr int TUNE_REPEATS = 5;
+// Timings within this fraction of the fastest count as equal (run-to-run
+// differences of the same configuration on one device reach about 1 %).
+constexpr double TUNE_TIE = 0.02;
 
 struct TuneTime {
   double median = 0.0;
@@ -1415,22 +1418,36 @@ extern "C" ripple_fv_status ripple_fv_batch_tune(ripple_fv_ctx* ctx, int32_t n,
     (void)hipGetLastError();
     return fail(ctx, RIPPLE_FV_E_NOMEM, "tuner state allocation failed");
   }
-  // The incumbent starts as the default configuration (SoA, library
-  // defaults) and is replaced only by a candidate whose median beats it by
-  // more than the larger of the two timings' spreads, so noise alone never
-  // moves the pick away from the default.
+  // Coordinate search in stages (layout; x-sweep workgroup; y/z chunk width
+  // and segment; x cells per y/z thread; fused or separate x-y; persistent
+  // launches), starting from the default (SoA, library defaults).  Each stage
+  // times the incumbent again beside its candidates, all built from the
+  // incumbent, and takes the first configuration in the order [incumbent,
+  // candidates in the listed order] whose median is within a tolerance of
+  // the stage's fastest median: the larger of the timings' largest spread
+  // and TUNE_TIE of the fastest median.  So the incumbent stays unless a
+  // candidate beats it by more than the tolerance, and configurations whose
+  // timings differ by less than the noise resolve the same way on every run.
   std::vector<ripple_fv_grid> best = base;
-  TuneTime best_t;
-  bool have_best = false;
-  auto consider = [&](std::vector<ripple_fv_grid> cand) -> ripple_fv_status {
+  auto stage = [&](const std::vector<std::vector<ripple_fv_grid>>& cands) -> ripple_fv_status {
     ripple_fv_status s2;
-    const TuneTime t = time_candidate(ctx, cand, W, s, &s2);
-    if (s2) return s2;
-    if (!have_best || t.median < best_t.median - std::max(best_t.spread, t.spread)) {
-      best_t = t;
-      best = cand;
-      have_best = true;
+    std::vector<std::vector<ripple_fv_grid>> order;
+    order.push_back(best);
+    order.insert(order.end(), cands.begin(), cands.end());
+    std::vector<TuneTime> t(order.size());
+    double fastest = 1e300, spread = 0.0;
+    for (size_t i = 0; i < order.size(); ++i) {
+      t[i] = time_candidate(ctx, order[i], W, s, &s2);
+      if (s2) return s2;
+      fastest = std::min(fastest, t[i].median);
+      spread = std::max(spread, t[i].spread);
     }
+    const double tol = std::max(spread, TUNE_TIE * fastest);
+    for (size_t i = 0; i < order.size(); ++i)
+      if (t[i].median <= fastest + tol) {
+        best = order[i];
+        break;
+      }
     return RIPPLE_FV_OK;
   };
   auto with = [&](auto edit) {
@@ -1438,39 +1455,46 @@ extern "C" ripple_fv_status ripple_fv_batch_tune(ripple_fv_ctx* ctx, int32_t n,
     for (auto& g : c) edit(g);
     return c;
   };
+  std::vector<std::vector<ripple_fv_grid>> cands;
   // 1. layout
-  const int layouts[5][2] = {{RIPPLE_FV_SOA, 0}, {RIPPLE_FV_AOS, 0}, {RIPPLE_FV_AOSOA, 16},
-                             {RIPPLE_FV_AOSOA, 32}, {RIPPLE_FV_AOSOA, 64}};
-  std::vector<ripple_fv_grid> start = best;
-  for (auto& L : layouts) {
-    std::vector<ripple_fv_grid> c = start;
-    for (auto& g : c) { g.layout = L[0]; g.aosoa_w = L[1]; }
-    if ((st = consider(c))) break;
-  }
+  const int layouts[4][2] = {{RIPPLE_FV_AOS, 0}, {RIPPLE_FV_AOSOA, 16}, {RIPPLE_FV_AOSOA, 32},
+                             {RIPPLE_FV_AOSOA, 64}};
+  for (auto& L : layouts)
+    cands.push_back(with([&](ripple_fv_grid& g) { g.layout = L[0]; g.aosoa_w = L[1]; }));
+  st = stage(cands);
   // 2. x sweep workgroup
-  for (int xb : {128, 256}) {
-    if (st) break;
-    st = consider(with([&](ripple_fv_grid& g) { g.x_block = xb; }));
+  if (!st) {
+    cands.clear();
+    cands.push_back(with([&](ripple_fv_grid& g) { g.x_block = 128; }));
+    st = stage(cands);
   }
-  // 3. y/z sweep chunk width and segment length
-  for (int yb : {64, 128, 256})
-    for (int sg : {16, 32, 64, 128}) {
-      if (st) break;
-      st = consider(with([&](ripple_fv_grid& g) { g.yz_block = yb; g.yz_segment = sg; }));
-    }
-  // 4. x cells per y/z thread, fused or separate x and y sweeps
-  for (int cols : {1, 2, 4}) {
-    if (st || base[0].dtype == RIPPLE_FV_F64) break;  // FP64 runs one cell per thread
-    st = consider(with([&](ripple_fv_grid& g) { g.yz_cols = cols; }));
+  // 3. y/z sweep chunk width and segment length (longer segments and wider
+  // chunks first: fewer tiles and fewer re-read halo cells)
+  if (!st) {
+    cands.clear();
+    for (int sg : {128, 64, 32, 16})
+      for (int yb : {256, 128, 64})
+        if (!(yb == 256 && sg == 128))
+          cands.push_back(with([&](ripple_fv_grid& g) { g.yz_block = yb; g.yz_segment = sg; }));
+    st = stage(cands);
   }
-  for (int split : {0, 1, 2, 3}) {
-    if (st) break;
-    st = consider(with([&](ripple_fv_grid& g) { g.split_xy = split; }));
+  // 4. x cells per y/z thread (FP32; FP64 runs one cell per thread), fused or
+  // separate x and y sweeps
+  if (!st && base[0].dtype != RIPPLE_FV_F64) {
+    cands.clear();
+    for (int cols : {1, 4}) cands.push_back(with([&](ripple_fv_grid& g) { g.yz_cols = cols; }));
+    st = stage(cands);
+  }
+  if (!st) {
+    cands.clear();
+    for (int split : {1, 2, 3}) cands.push_back(with([&](ripple_fv_grid& g) { g.split_xy = split; }));
+    st = stage(cands);
   }
   // 5. persistent launches
-  for (int pc : {0, 2, 4, 8}) {
-    if (st) break;
-    st = consider(with([&](ripple_fv_grid& g) { g.persist = pc; }));
+  if (!st) {
+    cands.clear();
+    for (int pc : {2, 4, 8}) cands.push_back(with([&](ripple_fv_grid& g) { g.persist = pc; }));
+    st = stage(cands);
   }
   hipFree(W);
   if (st) return st;
