@@ -1307,6 +1307,7 @@ namespace {
 
 struct TuneBufs {
   std::vector<void*> a, b;
+  std::vector<int64_t> bytes;
   ~TuneBufs() {
     for (void* p : a) if (p) hipFree(p);
     for (void* p : b) if (p) hipFree(p);
@@ -1330,30 +1331,25 @@ struct TuneTime {
 
 // Time the batch described by `cand` on a synthetic smooth state (one eager
 // warm-up step, one untimed graph run that captures the graph, then the
-// timed replays).
+// timed replays).  Every candidate runs in the same buffers (B, sized for
+// the largest layout of each grid), so no candidate gains or loses from
+// where its memory happens to lie.
 TuneTime time_candidate(ripple_fv_ctx* ctx, std::vector<ripple_fv_grid>& cand, double* W,
-                        hipStream_t s, ripple_fv_status* st) {
+                        TuneBufs& B, hipStream_t s, ripple_fv_status* st) {
   *st = RIPPLE_FV_OK;
   TuneTime out;
   const int n = (int)cand.size();
   for (auto& g : cand) {
     if (ripple_fv_grid_init(&g)) { *st = fail(ctx, RIPPLE_FV_E_INVALID, "tuner candidate"); return out; }
   }
-  TuneBufs B;
-  B.a.assign(n, nullptr);
-  B.b.assign(n, nullptr);
   for (int g = 0; g < n; ++g) {
-    if (hipMalloc(&B.a[g], cand[g].bytes) != hipSuccess || hipMalloc(&B.b[g], cand[g].bytes) != hipSuccess) {
-      (void)hipGetLastError();
-      *st = fail(ctx, RIPPLE_FV_E_NOMEM, "tuner buffer allocation failed");
-      return out;
-    }
+    if (cand[g].bytes > B.bytes[g]) { *st = fail(ctx, RIPPLE_FV_E_INVALID, "tuner buffer too small"); return out; }
     hipError_t e = launch_tune_state(W, cand[g].n, s);
     if (e == hipSuccess) e = launch_import(desc_of(cand[g], B.a[g]), W, 1, s);
     if (e != hipSuccess) { *st = fail(ctx, RIPPLE_FV_E_DEVICE, hipGetErrorString(e)); return out; }
   }
   auto drop_plan = [&]() {
-    // the candidate's plan refers to buffers that are about to be freed
+    // the candidate's plan refers to the tuner's buffers, freed when it returns
     const std::string key = plan_key(n, cand.data());
     ctx->plans.erase(key);
     for (auto it = ctx->plan_order.begin(); it != ctx->plan_order.end(); ++it)
@@ -1418,6 +1414,28 @@ extern "C" ripple_fv_status ripple_fv_batch_tune(ripple_fv_ctx* ctx, int32_t n,
     (void)hipGetLastError();
     return fail(ctx, RIPPLE_FV_E_NOMEM, "tuner state allocation failed");
   }
+  // one pair of buffers per grid, large enough for every layout tried
+  TuneBufs B;
+  B.a.assign(n, nullptr);
+  B.b.assign(n, nullptr);
+  B.bytes.assign(n, 0);
+  for (int g = 0; g < n && !st; ++g) {
+    for (int L : {RIPPLE_FV_SOA, RIPPLE_FV_AOS, RIPPLE_FV_AOSOA})
+      for (int w : {16, 32, 64}) {
+        ripple_fv_grid v = base[g];
+        v.layout = L;
+        v.aosoa_w = L == RIPPLE_FV_AOSOA ? w : 0;
+        if (ripple_fv_grid_init(&v) == RIPPLE_FV_OK) B.bytes[g] = std::max(B.bytes[g], v.bytes);
+      }
+    if (hipMalloc(&B.a[g], B.bytes[g]) != hipSuccess || hipMalloc(&B.b[g], B.bytes[g]) != hipSuccess) {
+      (void)hipGetLastError();
+      st = fail(ctx, RIPPLE_FV_E_NOMEM, "tuner buffer allocation failed");
+    }
+  }
+  if (st) {
+    hipFree(W);
+    return st;
+  }
   // Coordinate search in stages (layout; x-sweep workgroup; y/z chunk width
   // and segment; x cells per y/z thread; fused or separate x-y; persistent
   // launches), starting from the default (SoA, library defaults).  Each stage
@@ -1437,7 +1455,7 @@ extern "C" ripple_fv_status ripple_fv_batch_tune(ripple_fv_ctx* ctx, int32_t n,
     std::vector<TuneTime> t(order.size());
     double fastest = 1e300, spread = 0.0;
     for (size_t i = 0; i < order.size(); ++i) {
-      t[i] = time_candidate(ctx, order[i], W, s, &s2);
+      t[i] = time_candidate(ctx, order[i], W, B, s, &s2);
       if (s2) return s2;
       fastest = std::min(fastest, t[i].median);
       spread = std::max(spread, t[i].spread);

@@ -147,16 +147,32 @@ __device__ __forceinline__ const void* comp_base(const void* buf, int64_t q0, in
 template <typename T, int LAY>
 __device__ __forceinline__ void load_cell_rel(const void* buf, int64_t q0, int64_t ptot,
                                               uint32_t lane_bytes, T u[5]) {
+  if constexpr (LAY == LAY_AOS && sizeof(T) == 8) {
+    // a 40-byte FP64 cell (8-byte aligned) as 16 + 16 + 8 bytes: three
+    // accesses per lane instead of five
+    const void* b = comp_base<T, LAY>(buf, q0, 0, ptot);
+    gload_n<T, 2>(b, lane_bytes, u);
+    gload_n<T, 2>(b, lane_bytes + 16u, u + 2);
+    u[4] = gload<T>(b, lane_bytes + 32u);
+  } else {
 #pragma unroll
-  for (int c = 0; c < 5; ++c) u[c] = gload<T>(comp_base<T, LAY>(buf, q0, c, ptot), lane_bytes);
+    for (int c = 0; c < 5; ++c) u[c] = gload<T>(comp_base<T, LAY>(buf, q0, c, ptot), lane_bytes);
+  }
 }
 
 template <typename T, int LAY>
 __device__ __forceinline__ void store_cell_rel(void* buf, int64_t q0, int64_t ptot,
                                                uint32_t lane_bytes, const T u[5]) {
+  if constexpr (LAY == LAY_AOS && sizeof(T) == 8) {
+    void* b = const_cast<void*>(comp_base<T, LAY>(buf, q0, 0, ptot));
+    gstore_n<T, 2>(b, lane_bytes, u);
+    gstore_n<T, 2>(b, lane_bytes + 16u, u + 2);
+    gstore<T>(b, lane_bytes + 32u, u[4]);
+  } else {
 #pragma unroll
-  for (int c = 0; c < 5; ++c)
-    gstore<T>(const_cast<void*>(comp_base<T, LAY>(buf, q0, c, ptot)), lane_bytes, u[c]);
+    for (int c = 0; c < 5; ++c)
+      gstore<T>(const_cast<void*>(comp_base<T, LAY>(buf, q0, c, ptot)), lane_bytes, u[c]);
+  }
 }
 
 // COLS consecutive cells along x starting at cell q0 + r, r a multiple of COLS:
