@@ -585,6 +585,8 @@ def main():
                     help="run only the 256^3 FP64 layout leg (prints its JSON)")
     ap.add_argument("--batch-only", action="store_true",
                     help="run only the 64-grid batch leg (prints its JSON)")
+    ap.add_argument("--partition-only", action="store_true",
+                    help="run only the 768^3 2x2x2 sub-block leg (prints its JSON)")
     ap.add_argument("--no-force2d", action="store_true",
                     help="skip the 2D FORCE flux-difference leg")
     ap.add_argument("--force2d-only", action="store_true",
@@ -620,6 +622,10 @@ def main():
     pt_args = ([int(v) for v in args.particles_sizes.split(",")], args.particles_dtypes.split(","),
                args.particles_layouts.split(","), max(args.steps, 5), args.warmup)
     lay_args = (256, args.layout_steps, args.warmup, args.layouts.split(","))
+    if args.partition_only:
+        print(json.dumps({"partition_768_f32_2x2x2": run_partition_workload(args.steps, args.warmup)}),
+              flush=True)
+        return
     if args.batch_only:
         print(json.dumps({"batch_64_grids_f32": run_batch_workload(args.steps, args.warmup)}),
               flush=True)
