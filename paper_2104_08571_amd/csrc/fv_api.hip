@@ -81,9 +81,14 @@ struct PlanCore {
   int nhalo[3] = {0, 0, 0};
   int64_t halo_area[3] = {0, 0, 0};
   const DevGrid* h_grids = nullptr;
+  // dispatch orders of the batched y, z and fused x-y launches (slots of
+  // each; 0: none, each XCD then takes one contiguous run of the tiles)
+  const int32_t* order[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  int64_t nslots[5] = {0, 0, 0, 0, 0};
   // device copies and per-grid slots
   DevGrid* d_grids = nullptr;
   int64_t* d_tiles[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  int32_t* d_order[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   HaloTask* d_halo[3] = {nullptr, nullptr, nullptr};
   double* d_lam = nullptr;
   double* d_t = nullptr;
@@ -105,19 +110,25 @@ struct PlanCore {
 };
 
 // Byte offsets of the device workspace of a batch of n grids with nhalo[]
-// halo tasks per axis: descriptors, tile prefix sums, halo tasks, then the
-// per-grid dt / lambda / time / wave-speed slots (each part 256-byte aligned).
+// halo tasks per axis and nslots[] dispatch slots per launch kind (null: no
+// dispatch orders): descriptors, tile prefix sums, halo tasks, dispatch
+// orders, then the per-grid dt / lambda / time / wave-speed slots (each part
+// 256-byte aligned).
 struct WsLayout {
-  size_t grids, tiles[5], halo[3], lam, t, dt, s, total;
+  size_t grids, tiles[5], halo[3], order[5], lam, t, dt, s, total;
 };
 
-WsLayout ws_layout(int n, const int nhalo[3]) {
+WsLayout ws_layout(int n, const int nhalo[3], const int64_t* nslots) {
   auto align = [](size_t v) { return (v + 255) & ~size_t(255); };
   WsLayout L;
   size_t off = 0;
   L.grids = off; off = align(off + sizeof(DevGrid) * n);
   for (int k = 0; k < 5; ++k) { L.tiles[k] = off; off = align(off + sizeof(int64_t) * (n + 1)); }
   for (int k = 0; k < 3; ++k) { L.halo[k] = off; off = align(off + sizeof(HaloTask) * (nhalo[k] + 1)); }
+  for (int k = 0; k < 5; ++k) {
+    L.order[k] = off;
+    off = align(off + sizeof(int32_t) * (nslots ? nslots[k] : 0));
+  }
   L.lam = off; off = align(off + sizeof(double) * 3 * n);
   L.t = off; off = align(off + sizeof(double) * n);
   L.dt = off; off = align(off + sizeof(double) * n);
@@ -129,6 +140,8 @@ WsLayout ws_layout(int n, const int nhalo[3]) {
 void ws_bind(PlanCore& P, char* base, const WsLayout& L) {
   P.d_grids = reinterpret_cast<DevGrid*>(base + L.grids);
   for (int k = 0; k < 5; ++k) P.d_tiles[k] = reinterpret_cast<int64_t*>(base + L.tiles[k]);
+  for (int k = 0; k < 5; ++k)
+    P.d_order[k] = P.nslots[k] ? reinterpret_cast<int32_t*>(base + L.order[k]) : nullptr;
   for (int k = 0; k < 3; ++k) P.d_halo[k] = reinterpret_cast<HaloTask*>(base + L.halo[k]);
   P.d_lam = reinterpret_cast<double*>(base + L.lam);
   P.d_t = reinterpret_cast<double*>(base + L.t);
@@ -141,6 +154,7 @@ struct Plan : PlanCore {
   std::vector<ripple_fv_grid> grid_store;
   std::vector<int64_t> tile_store[5];
   std::vector<HaloTask> halo_store[3];
+  std::vector<int32_t> order_store[5];
   std::vector<DevGrid> h_grid_store;
   void* dmem = nullptr;                 // device workspace (one allocation)
   // descriptor staging for buffer-pointer updates
@@ -497,6 +511,24 @@ void plan_shape(PlanCore& P, int n, const ripple_fv_grid* grids, int64_t* const 
   P.h_grids = h_grids;
 }
 
+// Dispatch order of the batched launch of kind k (1: y sweep, 2: z sweep, 4:
+// fused x-y pass) from the cells each tile marches (dispatch_order in
+// fv_index.hpp); a tile costs those cells plus the 4 halo cells and about 2
+// of pipeline fill.
+void tile_order(const PlanCore& P, int k, std::vector<int32_t>& order) {
+  std::vector<int32_t> cost((size_t)P.tiles[k][P.n]);
+  for (int g = 0; g < P.n; ++g) {
+    const ripple_fv_grid& G = P.grids[g];
+    for (int64_t t = P.tiles[k][g]; t < P.tiles[k][g + 1]; ++t) {
+      const int64_t lt = t - P.tiles[k][g];
+      const int len = k == 4 ? tile_len_xy(G, P.seg_xy, lt)
+                             : tile_len_yz(G, k, P.tl.yz_block, P.tl.yz_segment, P.tl.yz_cols, lt);
+      cost[(size_t)t] = len + 2 * HALO + 2;
+    }
+  }
+  dispatch_order(cost, NXCD, order);
+}
+
 ripple_fv_status build_plan(ripple_fv_ctx* ctx, int n, const ripple_fv_grid* grids, Plan** out) {
   const std::string key = plan_key(n, grids);
   auto it = ctx->plans.find(key);
@@ -518,8 +550,15 @@ ripple_fv_status build_plan(ripple_fv_ctx* ctx, int n, const ripple_fv_grid* gri
   }
   P->h_grid_store.resize(n);
   plan_shape(*P, n, P->grid_store.data(), tiles, halo, P->h_grid_store.data());
+  for (int k : {1, 2, 4}) {
+    if (P->tiles[k][n] == 0) continue;
+    tile_order(*P, k, P->order_store[k]);
+    if (P->order_store[k].empty()) continue;
+    P->order[k] = P->order_store[k].data();
+    P->nslots[k] = (int64_t)P->order_store[k].size();
+  }
   // device workspace
-  const WsLayout L = ws_layout(n, P->nhalo);
+  const WsLayout L = ws_layout(n, P->nhalo, P->nslots);
   if (hipMalloc(&P->dmem, L.total) != hipSuccess) {
     (void)hipGetLastError();
     return fail(ctx, RIPPLE_FV_E_NOMEM, "plan workspace allocation failed");
@@ -531,6 +570,10 @@ ripple_fv_status build_plan(ripple_fv_ctx* ctx, int n, const ripple_fv_grid* gri
   for (int k = 0; k < 3; ++k)
     if (P->nhalo[k])
       HIP_OR_FAIL(ctx, hipMemcpy(P->d_halo[k], P->halo[k], sizeof(HaloTask) * P->nhalo[k],
+                                 hipMemcpyHostToDevice));
+  for (int k = 0; k < 5; ++k)
+    if (P->nslots[k])
+      HIP_OR_FAIL(ctx, hipMemcpy(P->d_order[k], P->order[k], sizeof(int32_t) * P->nslots[k],
                                  hipMemcpyHostToDevice));
   HIP_OR_FAIL(ctx, hipMemset(P->d_lam, 0, sizeof(double) * 3 * n));
   HIP_OR_FAIL(ctx, hipMemset(P->d_t, 0, sizeof(double) * n));
@@ -578,6 +621,27 @@ int blocks_for(const ripple_fv_ctx* ctx, const Tiling& tl, int64_t tiles) {
   int64_t b = tiles;
   if (tl.persist > 0) b = std::min<int64_t>(tiles, (int64_t)tl.persist * ctx->cu_count);
   return (int)std::max<int64_t>(1, std::min<int64_t>(b, 0x7fffffff));
+}
+
+// Workgroups of a launch through a dispatch order of `slots` entries (a
+// multiple of NXCD): one per slot, or with persistent launches as many as
+// fit, rounded down to a multiple of NXCD so that each workgroup's slots lie
+// on its own XCD.
+int blocks_for_slots(const ripple_fv_ctx* ctx, const Tiling& tl, int64_t slots) {
+  int64_t b = slots;
+  if (tl.persist > 0) b = std::min<int64_t>(slots, (int64_t)tl.persist * ctx->cu_count);
+  b = std::min<int64_t>(b, 0x7fffffff) / NXCD * NXCD;
+  return (int)std::max<int64_t>(NXCD, b);
+}
+
+// Set a batched launch of kind k over all tiles, through the plan's dispatch
+// order where it has one; returns the workgroup count.
+int batched_range(const ripple_fv_ctx* ctx, const PlanCore* P, int k, TileRange& r) {
+  r.first = 0;
+  r.count = P->tiles[k][P->n];
+  r.order = P->d_order[k];
+  r.slots = r.order ? P->nslots[k] : 0;
+  return r.order ? blocks_for_slots(ctx, P->tl, r.slots) : blocks_for(ctx, P->tl, r.count);
 }
 
 // Launches of one kernel kind, optionally bracketed by profiling events.
@@ -648,10 +712,8 @@ ripple_fv_status enqueue_sweep(ripple_fv_ctx* ctx, const PlanCore* P, Launcher& 
                                        blocks_for(ctx, P->tl, sp.tiles.count), L.s));
     }
   } else {
-    sp.tiles.first = 0;
-    sp.tiles.count = pre[P->n];
-    LAUNCH_OR_FAIL(ctx, launch_sweep(P->dtype, P->lay, axis, P->tl, sp,
-                                     blocks_for(ctx, P->tl, sp.tiles.count), L.s));
+    const int blocks = batched_range(ctx, P, axis, sp.tiles);
+    LAUNCH_OR_FAIL(ctx, launch_sweep(P->dtype, P->lay, axis, P->tl, sp, blocks, L.s));
   }
   return L.end(e1);
 }
@@ -682,10 +744,8 @@ ripple_fv_status enqueue_sweep_xy(ripple_fv_ctx* ctx, const PlanCore* P, Launche
                                           blocks_for(ctx, P->tl, sp.tiles.count), L.s));
     }
   } else {
-    sp.tiles.first = 0;
-    sp.tiles.count = pre[P->n];
-    LAUNCH_OR_FAIL(ctx, launch_sweep_xy(P->dtype, P->lay, P->tl, sp,
-                                        blocks_for(ctx, P->tl, sp.tiles.count), L.s));
+    const int blocks = batched_range(ctx, P, 4, sp.tiles);
+    LAUNCH_OR_FAIL(ctx, launch_sweep_xy(P->dtype, P->lay, P->tl, sp, blocks, L.s));
   }
   return L.end(e1);
 }
@@ -707,7 +767,7 @@ ripple_fv_status enqueue_wavespeed(ripple_fv_ctx* ctx, const PlanCore* P, Launch
   hipEvent_t e1 = nullptr;
   ripple_fv_status st = L.begin(RIPPLE_FV_K_WAVESPEED, &e1);
   if (st) return st;
-  TileRange tr;
+  TileRange tr{};
   tr.tile_start = P->d_tiles[3];
   const int64_t* pre = P->tiles[3];
   Tiling tl = P->tl;
@@ -1120,7 +1180,7 @@ ripple_fv_status ripple_fv_run_batch_noalloc(ripple_fv_ctx* ctx, int32_t n,
     hg[g].buf[0] = u[g];
     hg[g].buf[1] = work[g];
   }
-  const WsLayout L = ws_layout(n, P.nhalo);
+  const WsLayout L = ws_layout(n, P.nhalo, nullptr);
   if (L.total > SCRATCH_BYTES) return fail(ctx, RIPPLE_FV_E_INVALID, "workspace exceeds the scratch array");
   alignas(16) unsigned char img[SCRATCH_BYTES];
   std::memset(img, 0, L.total);  // dt, lambda, time and wave-speed slots start at zero

@@ -5,6 +5,9 @@
 
 #include <stdint.h>
 
+#include <algorithm>
+#include <vector>
+
 #if defined(__HIPCC__)
 #include <hip/hip_runtime.h>
 #define RFV_HD __host__ __device__ __forceinline__
@@ -63,6 +66,43 @@ RFV_HD XPos x_position(int tid, int F0, int lx, int ny, int nz) {
   r.dj = j - r.j0;
   r.dk = k - r.k0;
   return r;
+}
+
+// Dispatch order of a launch over tiles of the given costs, for a part whose
+// workgroups go round-robin to nxcd XCDs (workgroup w to XCD w mod nxcd), each
+// of which starts its workgroups in index order as CUs free up.  With tiles
+// of uneven cost (grids of different extents, short last segments), handing
+// each XCD an equal number of tiles leaves some XCDs working after the others
+// finish.  So the tile list is cut into nxcd contiguous runs of about equal
+// cost (each tile goes to the run that holds the midpoint of its share), one
+// per XCD, and each run is taken costliest tile first, ties in list order (a
+// grid's tiles stay neighbours and share halo cells in that XCD's L2).  Entry
+// s of `order` is the tile that slot s takes, -1 for none: slot s belongs to
+// XCD s mod nxcd, and there are nxcd times the longest run of slots.  Where
+// all tiles cost the same the order is left empty: equal runs in list order
+// are what a launch without one does (xcd_order).  Host only.
+inline void dispatch_order(const std::vector<int32_t>& cost, int nxcd, std::vector<int32_t>& order) {
+  order.clear();
+  if (cost.empty() ||
+      std::all_of(cost.begin(), cost.end(), [&](int32_t c) { return c == cost[0]; }))
+    return;
+  int64_t total = 0;
+  for (int32_t c : cost) total += c;
+  std::vector<std::vector<int32_t>> run((size_t)nxcd);
+  int64_t acc = 0;
+  for (size_t t = 0; t < cost.size(); ++t) {
+    const int64_t x = std::min<int64_t>(nxcd - 1, (2 * acc + cost[t]) * nxcd / (2 * total));
+    run[(size_t)x].push_back((int32_t)t);
+    acc += cost[t];
+  }
+  size_t longest = 0;
+  for (auto& r : run) {
+    std::stable_sort(r.begin(), r.end(), [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
+    longest = std::max(longest, r.size());
+  }
+  order.assign((size_t)nxcd * longest, -1);
+  for (size_t x = 0; x < run.size(); ++x)
+    for (size_t i = 0; i < run[x].size(); ++i) order[i * nxcd + x] = run[x][i];
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs.  Renumber them so

@@ -43,12 +43,21 @@ struct Work {
 };
 
 // Tiles of one sweep: tile_start[g] is the first tile of grid g, tile_start[ngrids]
-// the total.  A launch processes tiles [first, first + count).
+// the total.  A launch processes tiles [first, first + count).  With an order
+// table the launch has `slots` dispatch slots (a multiple of NXCD, as is its
+// workgroup count) and slot s takes tile first + order[s] (none where
+// order[s] < 0); without one, each XCD takes one contiguous run of the list.
 struct TileRange {
   const int64_t* tile_start;
   int64_t first;
   int64_t count;
+  const int32_t* order;
+  int64_t slots;
 };
+
+// XCDs of the part.  Workgroups are dispatched round-robin over them, in
+// workgroup-index order.
+constexpr int NXCD = 8;
 
 struct SweepParams {
   Work w;
@@ -101,6 +110,9 @@ bool xy_eligible(const ripple_fv_grid& g);
 // fits a workgroup, 3: wave strips).
 int xy_mode(int dtype, const ripple_fv_grid* grids, int n, int split_xy);
 int64_t tiles_xy(const ripple_fv_grid& g, int yz_segment, int xmode);
+int tile_len_yz(const ripple_fv_grid& g, int axis, int yz_block, int yz_segment, int yz_cols,
+                int64_t lt);
+int tile_len_xy(const ripple_fv_grid& g, int seg, int64_t lt);
 constexpr int WS_BLOCK = 256;
 constexpr int WS_CELLS_PER_THREAD = 4;
 

@@ -22,6 +22,8 @@
 // linked to a neighbouring sub-block read the padding that k_halo filled.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "fv_internal.hpp"
 #include "fv_index.hpp"
 #include "fv_layout.hpp"
@@ -41,6 +43,22 @@ __device__ __forceinline__ int find_grid(const int64_t* start, int n, int64_t t)
     if (start[mid] <= t) lo = mid; else hi = mid - 1;
   }
   return uniform(lo);
+}
+
+// Dispatch slots of a launch over a tile range, the first slot of this
+// workgroup, and the tile (relative to r.first) that slot b takes, -1 for
+// none.  With an order table workgroup w takes slots w, w + gridDim.x, ...,
+// all on the XCD that w is dispatched to (gridDim.x is a multiple of NXCD);
+// without one each XCD takes one contiguous run of the tile list, since
+// neighbouring tiles share halo cells and then share that XCD's L2.
+__device__ __forceinline__ int64_t slot_count(const TileRange& r) {
+  return r.order ? r.slots : r.count;
+}
+__device__ __forceinline__ int64_t first_slot(const TileRange& r) {
+  return r.order ? (int64_t)blockIdx.x : xcd_order(blockIdx.x, gridDim.x);
+}
+__device__ __forceinline__ int64_t slot_tile(const TileRange& r, int64_t b) {
+  return r.order ? (int64_t)r.order[b] : b;
 }
 
 
@@ -104,8 +122,10 @@ __global__ void __launch_bounds__(NT) k_sweep_x(SweepParams p, const DevGrid* __
   __shared__ T sA[5][NT];
   __shared__ T sB[5][NT];
   const int tid = threadIdx.x;
-  for (int64_t b = xcd_order(blockIdx.x, gridDim.x); b < p.tiles.count; b += gridDim.x) {
-    const int64_t gt = uniform(p.tiles.first + b);
+  for (int64_t b = first_slot(p.tiles); b < slot_count(p.tiles); b += gridDim.x) {
+    const int64_t tb = slot_tile(p.tiles, b);
+    if (tb < 0) continue;
+    const int64_t gt = uniform(p.tiles.first + tb);
     const int g = find_grid(tile_start, p.w.ngrids, gt);
     const DevGrid& G = grids[g];
     const int lt = (int)(gt - tile_start[g]);
@@ -205,8 +225,10 @@ __global__ void __launch_bounds__(256) k_sweep_yz(SweepParams p, const DevGrid* 
   __shared__ T red[3 * 16];
   const int nt = blockDim.x;
   const int tid = threadIdx.x;
-  for (int64_t b = xcd_order(blockIdx.x, gridDim.x); b < p.tiles.count; b += gridDim.x) {
-    const int64_t gt = uniform(p.tiles.first + b);
+  for (int64_t b = first_slot(p.tiles); b < slot_count(p.tiles); b += gridDim.x) {
+    const int64_t tb = slot_tile(p.tiles, b);
+    if (tb < 0) continue;
+    const int64_t gt = uniform(p.tiles.first + tb);
     const int g = find_grid(tile_start, p.w.ngrids, gt);
     const DevGrid& G = grids[g];
     const int64_t lt = gt - tile_start[g];
@@ -449,8 +471,10 @@ __global__ void __launch_bounds__(XM == XM_WAVES ? XY_WAVE_THREADS : XY_THREADS)
   __shared__ T sR[5][LN];
   __shared__ T sF[5][LN];
   const int tid = threadIdx.x;
-  for (int64_t b = xcd_order(blockIdx.x, gridDim.x); b < p.tiles.count; b += gridDim.x) {
-    const int64_t gt = uniform(p.tiles.first + b);
+  for (int64_t b = first_slot(p.tiles); b < slot_count(p.tiles); b += gridDim.x) {
+    const int64_t tb = slot_tile(p.tiles, b);
+    if (tb < 0) continue;
+    const int64_t gt = uniform(p.tiles.first + tb);
     const int g = find_grid(tile_start, p.w.ngrids, gt);
     const DevGrid& G = grids[g];
     const int lt = (int)(gt - tile_start[g]);
@@ -784,8 +808,10 @@ __global__ void __launch_bounds__(WS_BLOCK) k_wavespeed(Work w, int in, TileRang
                                                         const DevGrid* __restrict__ grids,
                                                         const int64_t* __restrict__ tile_start) {
   __shared__ T red[3 * 16];
-  for (int64_t b = xcd_order(blockIdx.x, gridDim.x); b < tr.count; b += gridDim.x) {
-    const int64_t gt = uniform(tr.first + b);
+  for (int64_t b = first_slot(tr); b < slot_count(tr); b += gridDim.x) {
+    const int64_t tb = slot_tile(tr, b);
+    if (tb < 0) continue;
+    const int64_t gt = uniform(tr.first + tb);
     const int g = find_grid(tile_start, w.ngrids, gt);
     const DevGrid& G = grids[g];
     const int64_t lt = gt - tile_start[g];
@@ -1166,6 +1192,30 @@ int64_t tiles_xy(const ripple_fv_grid& g, int yz_segment, int xmode) {
   }
   const int64_t rows = XY_THREADS / xy_row_lanes(g);
   return (g.n[2] + rows - 1) / rows * nseg;
+}
+
+// Cells along the sweep axis that tile lt of a grid marches (its segment's
+// length), in the tile numbering the kernels decode.
+int tile_len_yz(const ripple_fv_grid& g, int axis, int yz_block, int yz_segment, int yz_cols,
+                int64_t lt) {
+  const int nd = g.n[axis];
+#if RFV_YZ_ORDER
+  const int64_t ngroups = (int64_t)((g.n[0] + yz_cols - 1) / yz_cols) * g.n[axis == 1 ? 2 : 1];
+  const int64_t nchunk = (ngroups + yz_block - 1) / yz_block;
+  const int s = (int)(lt / nchunk);
+#else
+  (void)yz_block;
+  (void)yz_cols;
+  const int64_t nseg = (nd + yz_segment - 1) / yz_segment;
+  const int s = (int)(lt % nseg);
+#endif
+  return std::min(yz_segment, nd - s * yz_segment);
+}
+
+int tile_len_xy(const ripple_fv_grid& g, int seg, int64_t lt) {
+  const int64_t nseg = (g.n[1] + seg - 1) / seg;
+  const int s = (int)(lt % nseg);
+  return std::min(seg, g.n[1] - s * seg);
 }
 
 int64_t tiles_ws(const ripple_fv_grid& g) {

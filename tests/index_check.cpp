@@ -1,8 +1,12 @@
 // Host check of the sweeps' index arithmetic (fv_index.hpp) against its plain
-// definition: divisions of the flattened position.  Prints "ok" or the first
-// mismatch and exits non-zero.
+// definition: divisions of the flattened position; and of the launches'
+// dispatch orders against the properties that define them.  Prints "ok" or
+// the first mismatch and exits non-zero.
+#include <cstdint>
 #include <cstdio>
+#include <cstdlib>
 #include <initializer_list>
+#include <vector>
 
 #include "fv_index.hpp"
 
@@ -48,8 +52,87 @@ static int check_face() {
   return 0;
 }
 
+// dispatch_order: every tile exactly once; XCD x takes slots x, x + nxcd, ...
+// with its empty slots last; its tiles are one contiguous run of the list,
+// the runs in list order, each costliest first with ties in list order, and
+// each run's cost within one tile's cost of an equal share.
+static int check_order(const std::vector<int32_t>& cost, int nxcd) {
+  std::vector<int32_t> order;
+  dispatch_order(cost, nxcd, order);
+  const int64_t T = (int64_t)cost.size();
+  bool uniform = true;
+  int32_t cmax = 0;
+  int64_t total = 0;
+  for (int32_t c : cost) {
+    uniform = uniform && c == cost[0];
+    cmax = c > cmax ? c : cmax;
+    total += c;
+  }
+  if (uniform) {
+    if (!order.empty()) { std::printf("dispatch_order: uniform costs gave an order\n"); return 1; }
+    return 0;
+  }
+  if (order.size() % nxcd) { std::printf("dispatch_order: %zu slots\n", order.size()); return 1; }
+  std::vector<int> seen((size_t)T, 0);
+  const size_t per = order.size() / nxcd;
+  int64_t next = 0;  // first tile of the next run
+  size_t longest = 0;
+  for (int x = 0; x < nxcd; ++x) {
+    std::vector<int32_t> r;
+    bool ended = false;
+    for (size_t i = 0; i < per; ++i) {
+      const int32_t t = order[i * nxcd + x];
+      if (t < 0) { ended = true; continue; }
+      if (ended || t >= T || seen[t]++) { std::printf("dispatch_order: bad slot %zu\n", i * nxcd + x); return 1; }
+      r.push_back(t);
+    }
+    longest = r.size() > longest ? r.size() : longest;
+    int64_t lo = T, hi = -1, rc = 0;
+    for (size_t i = 0; i < r.size(); ++i) {
+      lo = r[i] < lo ? r[i] : lo;
+      hi = r[i] > hi ? r[i] : hi;
+      rc += cost[r[i]];
+      if (i && (cost[r[i]] > cost[r[i - 1]] || (cost[r[i]] == cost[r[i - 1]] && r[i] < r[i - 1]))) {
+        std::printf("dispatch_order: run %d not costliest first\n", x);
+        return 1;
+      }
+    }
+    if (!r.empty() && (lo != next || hi - lo + 1 != (int64_t)r.size())) {
+      std::printf("dispatch_order: run %d not contiguous from %lld\n", x, (long long)next);
+      return 1;
+    }
+    next += (int64_t)r.size();
+    if (std::llabs(rc * nxcd - total) > (int64_t)cmax * nxcd) {
+      std::printf("dispatch_order: run %d costs %lld of %lld\n", x, (long long)rc, (long long)total);
+      return 1;
+    }
+  }
+  if (next != T || longest != per) { std::printf("dispatch_order: runs cover %lld of %lld\n", (long long)next, (long long)T); return 1; }
+  return 0;
+}
+
+static int check_orders() {
+  uint64_t s = 2104;
+  auto rnd = [&](int m) {
+    s = s * 6364136223846793005ULL + 1442695040888963407ULL;
+    return (int)((s >> 33) % (uint64_t)m);
+  };
+  for (int trial = 0; trial < 400; ++trial) {
+    const int T = 1 + rnd(trial < 200 ? 40 : 4000);
+    const int kind = rnd(3);
+    std::vector<int32_t> cost((size_t)T);
+    for (int t = 0; t < T; ++t)
+      cost[t] = kind == 0 ? 6 + rnd(129)                    // any length
+                : kind == 1 ? (t % 5 == 4 ? 6 + rnd(64) : 134)  // full segments, short last ones
+                            : 70;                           // uniform
+    if (check_order(cost, 8) || check_order(cost, 3)) return 1;
+  }
+  return 0;
+}
+
 int main() {
   if (check_face()) return 1;
+  if (check_orders()) return 1;
   const int nxs[] = {1, 2, 3, 5, 17, 32, 61, 124, 125, 252, 253, 256, 300, 512};
   const int nys[] = {1, 3, 7, 16};
   const int nzs[] = {1, 2, 5};

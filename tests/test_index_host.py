@@ -1,6 +1,9 @@
 """The sweeps' index arithmetic (csrc/fv_index.hpp), compiled for the host
 with g++ and checked against its plain definition over many grid shapes,
-chunk sizes and boundary modes.  No GPU needed."""
+chunk sizes and boundary modes; and the batched launches' dispatch orders,
+checked on random tile costs against the properties that define them (each
+tile once, one contiguous run per XCD of about equal cost, costliest first).
+No GPU needed."""
 import os
 import shutil
 import subprocess
