@@ -34,9 +34,9 @@ PEAK_HBM_GBS = 8000.0
 PEAK_VALU_TFLOPS = 78.6
 # Arithmetic of one cell update along one axis, counted from the formulas the
 # kernels evaluate (add, sub, mul, min, max, median, reciprocal and square root
-# 1 each, fused multiply-add 2): slopes and Hancock half step 89, HLLC face
-# flux 78 (the star-state correction formed from g - 1), conservative update 15.
-FLOPS_PER_CELL_AXIS = 182
+# 1 each, fused multiply-add 2): slopes and Hancock half step 88, HLLC face
+# flux 74 (the star-state correction formed from g - 1), conservative update 15.
+FLOPS_PER_CELL_AXIS = 177
 CSRC = os.path.join(ROOT, "paper_2104_08571_amd", "csrc")
 PROFILES = os.path.join(ROOT, "profiles")
 

@@ -100,26 +100,36 @@ __device__ __forceinline__ void flux(const T u[5], T un, T p, T f[5]) {
 // state u0 and its backward / forward differences dm = U_i - U_{i-1},
 // dp = U_{i+1} - U_i, produce the evolved boundary states bl = Ub^L_i and
 // br = Ub^R_i.  hl = (dt/dx) / 2.
+//
+// The flux difference F(U^L) - F(U^R) is formed component by component
+// rather than from the two flux vectors, with the same value up to rounding:
+// the mass component is -s_n (U^L - U^R = -s), and each product difference
+// a b - a' b' is one fused multiply-add on the negated second product.
 template <typename T, int D>
 __device__ __forceinline__ void hancock(const T u0[5], const T dm[5], const T dp[5], T hl,
                                         T bl[5], T br[5]) {
-  T ul[5], ur[5];
+  T s[5], ul[5], ur[5];
 #pragma unroll
   for (int c = 0; c < 5; ++c) {
-    const T s = Arith<T>::minmod(dm[c], dp[c]);
-    ul[c] = fma_(T(-0.5), s, u0[c]);  // s/2 is exact: one rounding, as u0 - s/2
-    ur[c] = fma_(T(0.5), s, u0[c]);
+    s[c] = Arith<T>::minmod(dm[c], dp[c]);
+    ul[c] = fma_(T(-0.5), s[c], u0[c]);  // s/2 is exact: one rounding, as u0 - s/2
+    ur[c] = fma_(T(0.5), s[c], u0[c]);
   }
   const T rl = Arith<T>::recip(ul[0]);
   const T rr = Arith<T>::recip(ur[0]);
-  T fl[5], fr[5];
-  flux<T, D>(ul, ul[1 + D] * rl, pressure(ul, rl), fl);
-  flux<T, D>(ur, ur[1 + D] * rr, pressure(ur, rr), fr);
+  const T unl = ul[1 + D] * rl, unr = ur[1 + D] * rr;
+  const T pl = pressure(ul, rl), pr = pressure(ur, rr);
+  T d[5];
+  d[0] = -s[1 + D];
+#pragma unroll
+  for (int c = 1; c < 4; ++c)
+    if (c != 1 + D) d[c] = fma_(ul[c], unl, -(ur[c] * unr));
+  d[1 + D] = fma_(ul[1 + D], unl, pl) - fma_(ur[1 + D], unr, pr);
+  d[4] = fma_(unl, ul[4] + pl, -(unr * (ur[4] + pr)));
 #pragma unroll
   for (int c = 0; c < 5; ++c) {
-    const T d = fl[c] - fr[c];
-    bl[c] = fma_(hl, d, ul[c]);
-    br[c] = fma_(hl, d, ur[c]);
+    bl[c] = fma_(hl, d[c], ul[c]);
+    br[c] = fma_(hl, d[c], ur[c]);
   }
 }
 
@@ -138,7 +148,10 @@ __device__ __forceinline__ void hancock(const T u0[5], const T dm[5], const T dp
 //     mass and tangential momenta    (g - 1) U_k
 //     normal momentum                rho_k g S* - m_k
 //     energy                         (g - 1) E_k + (S* - u_k) (rho_k g S* + p_k q)
-//   (p_k / (rho_k (S_k - u_k)) times rho_k g is p_k q).
+//   (p_k / (rho_k (S_k - u_k)) times rho_k g is p_k q);
+//   the tangential momentum and energy fluxes u_k m + S_c (g - 1) m and
+//   u_k (E_k + p_k) + S_c (g - 1) E_k + ... share the factor
+//   w = u_k + S_c (g - 1): m w and E_k w + u_k p_k + ....
 template <typename T, int D>
 __device__ __forceinline__ void hllc(const T ul[5], const T ur[5], T f[5]) {
   using A = Arith<T>;
@@ -167,18 +180,18 @@ __device__ __forceinline__ void hllc(const T ul[5], const T ur[5], T f[5]) {
   const T Sk = left ? SL : SR;
   const T Sc = left ? A::min(SL, T(0)) : A::max(SR, T(0));
 
-  T fk[5];
-  flux<T, D>(uk, unk, pk, fk);
   const T q = A::recip(Sk - Ss);
   const T d = Ss - unk;                      // S* - u_k
   const T gm = d * q;                        // g - 1
   const T rs = fma_(uk[0], gm, uk[0]);       // rho*_k = rho_k g
   const T sg = Sc * gm;
+  const T w = unk + sg;
+  f[0] = fma_(sg, uk[0], uk[1 + D]);
 #pragma unroll
-  for (int c = 0; c < 4; ++c)
-    if (c != 1 + D) f[c] = fma_(sg, uk[c], fk[c]);
-  f[1 + D] = fma_(Sc, fma_(rs, Ss, -uk[1 + D]), fk[1 + D]);
-  f[4] = fma_(Sc, fma_(d, fma_(rs, Ss, pk * q), uk[4] * gm), fk[4]);
+  for (int c = 1; c < 4; ++c)
+    if (c != 1 + D) f[c] = uk[c] * w;
+  f[1 + D] = fma_(Sc, fma_(rs, Ss, -uk[1 + D]), fma_(uk[1 + D], unk, pk));
+  f[4] = fma_(Sc * d, fma_(rs, Ss, pk * q), fma_(unk, pk, uk[4] * w));
 }
 
 // Conservative update U' = U - lam (F_{i+1/2} - F_{i-1/2}).

@@ -43,8 +43,8 @@ def test_roofline_of_a_single_sweep_is_hbm_bound():
 
 
 def test_flops_per_cell_is_the_sum_of_the_counted_steps():
-    # slopes and Hancock half step 89, HLLC face flux 78, update 15
-    assert bench.FLOPS_PER_CELL_AXIS == 89 + 78 + 15
+    # slopes and Hancock half step 88, HLLC face flux 74, update 15
+    assert bench.FLOPS_PER_CELL_AXIS == 88 + 74 + 15
 
 
 def test_traffic_is_reported_only_for_the_sources_it_was_measured_on(tmp_path, monkeypatch):
