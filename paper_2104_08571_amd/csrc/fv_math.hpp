@@ -36,6 +36,11 @@ template <> struct Arith<float> {
     return a * __builtin_amdgcn_rcpf(b);
   }
   static __device__ __forceinline__ float root(float x) { return __builtin_amdgcn_sqrtf(x); }
+  // 1/a and 1/b: two hardware reciprocals
+  static __device__ __forceinline__ void recip2(float a, float b, float& ra, float& rb) {
+    ra = __builtin_amdgcn_rcpf(a);
+    rb = __builtin_amdgcn_rcpf(b);
+  }
   static __device__ __forceinline__ float min(float a, float b) { return __builtin_fminf(a, b); }
   static __device__ __forceinline__ float max(float a, float b) { return __builtin_fmaxf(a, b); }
   // minmod(a, b) is the median of (a, b, 0).
@@ -57,6 +62,13 @@ template <> struct Arith<double> {
     return __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
   }
   static __device__ __forceinline__ double quot(double a, double b) { return a * recip(b); }
+  // 1/a and 1/b from one refined reciprocal of a b (a few ulp; positive a, b
+  // whose product stays finite and normal: the sweeps' densities)
+  static __device__ __forceinline__ void recip2(double a, double b, double& ra, double& rb) {
+    const double r = recip(a * b);
+    ra = b * r;
+    rb = a * r;
+  }
   static __device__ __forceinline__ double root(double x) {
     const double h = 0.5 * x;
     double y = __builtin_amdgcn_rsq(x);
@@ -115,8 +127,8 @@ __device__ __forceinline__ void hancock(const T u0[5], const T dm[5], const T dp
     ul[c] = fma_(T(-0.5), s[c], u0[c]);  // s/2 is exact: one rounding, as u0 - s/2
     ur[c] = fma_(T(0.5), s[c], u0[c]);
   }
-  const T rl = Arith<T>::recip(ul[0]);
-  const T rr = Arith<T>::recip(ur[0]);
+  T rl, rr;
+  Arith<T>::recip2(ul[0], ur[0], rl, rr);
   const T unl = ul[1 + D] * rl, unr = ur[1 + D] * rr;
   const T pl = pressure(ul, rl), pr = pressure(ur, rr);
   T d[5];
@@ -155,8 +167,8 @@ __device__ __forceinline__ void hancock(const T u0[5], const T dm[5], const T dp
 template <typename T, int D>
 __device__ __forceinline__ void hllc(const T ul[5], const T ur[5], T f[5]) {
   using A = Arith<T>;
-  const T rl = A::recip(ul[0]);
-  const T rr = A::recip(ur[0]);
+  T rl, rr;
+  A::recip2(ul[0], ur[0], rl, rr);
   const T mL = ul[1 + D], mR = ur[1 + D];
   const T uL = mL * rl;
   const T uR = mR * rr;
