@@ -45,8 +45,8 @@ def test_fused_equals_split(dtype, layout, w, cols):
 
 
 @pytest.mark.parametrize("dtype", [R.F32, R.F64], ids=["f32", "f64"])
-@pytest.mark.parametrize("nx", [2, 3, 16, 17, 56, 57, 58, 59, 60, 61, 62, 119, 120, 121, 255, 300,
-                                508, 509, 512, 513, 520, 1000, 1016, 1017, 1100])
+@pytest.mark.parametrize("nx", [2, 3, 16, 17, 56, 57, 58, 59, 60, 61, 62, 119, 120, 121, 176, 192,
+                                255, 300, 384, 385, 508, 509, 512, 513, 520, 1000, 1016, 1017, 1100])
 def test_fused_row_lengths(dtype, nx):
     """Row lengths from 2 to 1100 cells: below, inside and above what one
     workgroup holds and around multiples of the 60-cell strip (fused where
@@ -59,34 +59,61 @@ def test_fused_row_lengths(dtype, nx):
         assert_forms_equal(shape, dtype, R.SOA, 0, bc, 2, 0, state=state)
 
 
-def test_linked_sub_blocks_match_whole_grid():
-    """Sub-blocks linked along y, along x, and along both (so the fused pass
-    reads corner padding), fused and split, match the whole grid bitwise; the
-    single fused sweep entry point reports a linked grid unsupported."""
-    shape = (40, 24, 10)   # sub-block rows of 20 or 40 cells: fused
-    whole = R.make_grid(shape, dtype=R.F64, layout=R.SOA, bc=(1, 0, 1))
-    W = ist.smooth_periodic(shape, seed=77)
-    (ref,), (t_ref,) = G.run(whole, W, 3)
-    for parts, split in (((1, 2, 1), 0), ((2, 1, 1), 0), ((2, 2, 1), 0), ((2, 3, 2), 0),
-                         ((2, 2, 1), 1), ((1, 2, 1), 3), ((2, 1, 1), 3), ((2, 3, 2), 3),
-                         ((2, 2, 1), 2)):
+def assert_partitions_match(shape, dtype, bc, seed, cases, nsteps=3):
+    """Each (parts, split_xy) partition of the grid, run as linked sub-blocks,
+    equals the whole grid bitwise."""
+    whole = R.make_grid(shape, dtype=dtype, layout=R.SOA, bc=bc)
+    W = ist.smooth_periodic(shape, seed=seed)
+    (ref,), (t_ref,) = G.run(whole, W, nsteps)
+    for parts, split in cases:
         subs = [R.copy_grid(sb, split_xy=split) for sb in R.ripple_fv_partition(whole, parts)]
         states, origins = [], []
         for idx, sb in enumerate(subs):
             a, b, c = idx % parts[0], (idx // parts[0]) % parts[1], idx // (parts[0] * parts[1])
             o = [k * (n // m) + min(k, n % m) for k, n, m in zip((a, b, c), shape, parts)]
             origins.append(o)
-            states.append(ist.smooth_periodic(list(sb.n), 77, origin=o, n_global=shape))
-        outs, ts = G.run(subs, states, 3)
+            states.append(ist.smooth_periodic(list(sb.n), seed, origin=o, n_global=shape))
+        outs, ts = G.run(subs, states, nsteps)
         for sb, U, o, t in zip(subs, outs, origins, ts):
             assert t == t_ref
             part = ref[:, o[2]:o[2] + sb.n[2], o[1]:o[1] + sb.n[1], o[0]:o[0] + sb.n[0]]
-            assert np.array_equal(U, part), (parts, o)
+            assert np.array_equal(U, part), (shape, parts, split, o)
+    return whole
+
+
+def test_linked_sub_blocks_match_whole_grid():
+    """Sub-blocks linked along y, along x, and along both (so the fused pass
+    reads corner padding), fused and split, match the whole grid bitwise; the
+    single fused sweep entry point reports a linked grid unsupported."""
+    shape = (40, 24, 10)   # sub-block rows of 20 or 40 cells: fused
+    whole = assert_partitions_match(
+        shape, R.F64, (1, 0, 1), 77,
+        (((1, 2, 1), 0), ((2, 1, 1), 0), ((2, 2, 1), 0), ((2, 3, 2), 0), ((2, 2, 1), 1),
+         ((1, 2, 1), 3), ((2, 1, 1), 3), ((2, 3, 2), 3), ((2, 2, 1), 2)))
     sub = R.ripple_fv_partition(whole, (1, 2, 1))[0]
     a, b = G.buffer(sub), G.buffer(sub)
     with pytest.raises(R.RippleFVError) as e:
         R.ripple_fv_sweep(G.ctx(), sub, R.AXIS_XY, a.data_ptr(), b.data_ptr(), 1e-3, G.stream())
     assert e.value.status == R.E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("shape,bc,cases", [
+    # rows of 20 and 40 cells (several per workgroup, four ghost lanes each);
+    # x periodic (both faces of every sub-block linked) and x transmissive
+    # (the outer faces physical)
+    ((40, 24, 10), (1, 0, 1), (((2, 1, 1), 0), ((2, 2, 1), 0), ((2, 3, 2), 0), ((2, 2, 1), 2))),
+    ((40, 24, 10), (0, 1, 0), (((2, 1, 1), 0), ((2, 2, 2), 2), ((2, 1, 1), 3))),
+    # rows of 384 cells (the 768^3 partition's sub-block rows): strips (0)
+    # and rows of 388 lanes (2)
+    ((768, 10, 6), (1, 1, 1), (((2, 1, 1), 0), ((2, 2, 1), 2))),
+    ((768, 10, 6), (0, 0, 1), (((2, 1, 1), 0), ((2, 1, 1), 2))),
+    # rows of 400 cells: rows of 404 lanes (2) and strips (0, 3)
+    ((800, 10, 6), (1, 0, 1), (((2, 1, 1), 2), ((2, 1, 1), 0), ((2, 1, 1), 3))),
+], ids=["r20p", "r20t", "r384p", "r384t", "r400"])
+def test_linked_sub_blocks_f32_row_forms(shape, bc, cases):
+    """FP32 sub-blocks linked along x in each form of the fused pass match
+    the whole grid bitwise."""
+    assert_partitions_match(shape, R.F32, bc, 91, cases)
 
 
 @pytest.mark.parametrize("dtype", [R.F32, R.F64], ids=["f32", "f64"])
