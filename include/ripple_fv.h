@@ -118,9 +118,9 @@ enum ripple_fv_kernel_kind {
  *           yz_segment: cells each y/z thread advances (>= 4; 0 = 128);
  *           persist: workgroups per CU of persistent launches (0 = one per tile);
  *           yz_cols: adjacent x cells per thread of the separate y and z
- *           sweeps (1, 2; 0 = 2 for FP32 SoA/AoSoA, else 1); FP64 always
- *           runs 1 (2 is accepted and means 1); the fused x-y sweep always
- *           runs one cell per thread;
+ *           sweeps (1, 2, 4; 0 = 2 for FP32 SoA/AoSoA, else 1); FP32 AoS
+ *           runs 2 for 4; FP64 always runs 1 (2 and 4 are accepted and mean
+ *           1); the fused x-y sweep always runs one cell per thread;
  *           split_xy: how the x and y sweeps run.  0 = as one fused pass
  *           wherever every grid of the batch allows it (n[0] >= 16), in the
  *           form that occupies fewer vector lanes per cell by a measured
