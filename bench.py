@@ -318,7 +318,12 @@ def run_shock_bubble_workload(sizes, dtypes, steps, warmup):
 PAPER_PARTICLE_MS = {"soa": {100_000: 0.0191, 1_000_000: 0.1036, 10_000_000: 0.8679,
                              20_000_000: 1.7146, 40_000_000: 3.4062, 80_000_000: 6.7914},
                      "aos": {100_000: 0.0259, 1_000_000: 0.1620, 10_000_000: 1.4472,
-                             20_000_000: 2.8487, 40_000_000: 5.7184, 80_000_000: 11.452}}
+                             20_000_000: 2.8487, 40_000_000: 5.7184, 80_000_000: 11.452},
+                     # shared-memory variants of the same table (strided, contiguous)
+                     "soa_lds": {100_000: 0.0221, 1_000_000: 0.1343, 10_000_000: 1.1834,
+                                 20_000_000: 2.3441, 40_000_000: 4.6741, 80_000_000: 9.3259},
+                     "aos_lds": {100_000: 0.0379, 1_000_000: 0.2381, 10_000_000: 2.0507,
+                                 20_000_000: 4.0743, 40_000_000: 8.1453, 80_000_000: 16.3081}}
 
 
 def run_particle_workload(sizes, dtypes, layouts, reps, warmup):
@@ -331,7 +336,10 @@ def run_particle_workload(sizes, dtypes, layouts, reps, warmup):
 
     ctx = R.ripple_fv_create(0)
     stream = torch.cuda.current_stream()
-    lays = {"soa": (R.SOA, 0), "aos": (R.AOS, 0), "aosoa64": (R.AOSOA, 64)}
+    # name: (layout, aosoa_w, stage); "_lds": staged through LDS with direct
+    # global-to-LDS loads
+    lays = {"soa": (R.SOA, 0, 0), "aos": (R.AOS, 0, 0), "aosoa64": (R.AOSOA, 64, 0),
+            "soa_lds": (R.SOA, 0, 1), "aos_lds": (R.AOS, 0, 1)}
     rows = []
     try:
         for dt_name in dtypes:
@@ -340,7 +348,7 @@ def run_particle_workload(sizes, dtypes, layouts, reps, warmup):
             for lay_name in layouts:
                 for n in sizes:
                     p = R.make_particles(n, dtype=dtype, layout=lays[lay_name][0],
-                                         aosoa_w=lays[lay_name][1])
+                                         aosoa_w=lays[lay_name][1], stage=lays[lay_name][2])
                     buf = torch.empty(p.bytes, dtype=torch.uint8, device="cuda")
                     gen = torch.Generator(device="cuda").manual_seed(n)
                     src = torch.rand((6, n), dtype=torch.float64, device="cuda", generator=gen)
@@ -601,7 +609,7 @@ def main():
     ap.add_argument("--shock-bubble-steps", type=int, default=1000)
     ap.add_argument("--no-particles", action="store_true", help="skip the particle-update leg")
     ap.add_argument("--particles-sizes", default="100000,1000000,10000000,20000000,40000000,80000000")
-    ap.add_argument("--particles-layouts", default="soa,aos,aosoa64")
+    ap.add_argument("--particles-layouts", default="soa,aos,aosoa64,soa_lds,aos_lds")
     ap.add_argument("--particles-dtypes", default="f32,f64")
     ap.add_argument("--particles-only", action="store_true",
                     help="run only the particle-update leg (prints its JSON)")

@@ -32,7 +32,11 @@ extern "C" {
  *  layout, dtype, aosoa_w   storage as in ripple_fv.h
  *  block    threads per workgroup (64, 128, 256, 512, 1024; 0 = 256);
  *           never changes results
- *  reserved must be 0
+ *  stage    0: each lane loads its particles into registers; 1: each wave
+ *           first copies its particles into LDS with direct global-to-LDS
+ *           loads (the paper's shared-memory variants, "ss" and "cs" of
+ *           table "tab:particle_update") and computes from there; never
+ *           changes results
  *  slots, bytes   OUT
  *
  * Storage.  Component c of particle k -- c = 0, 1, 2 the position x, y, z,
@@ -48,14 +52,14 @@ typedef struct ripple_particles {
   int32_t dtype;
   int32_t aosoa_w;
   int32_t block;
-  int32_t reserved;
+  int32_t stage;
   int32_t pad_;
   int64_t slots;
   int64_t bytes;
 } ripple_particles;
 
 /* Validate a descriptor and fill slots and bytes.  E_INVALID on n out of
- * range, unknown enums, bad aosoa_w or block, or a nonzero reserved field. */
+ * range, unknown enums, bad aosoa_w, block or stage. */
 ripple_fv_status ripple_particles_init(ripple_particles* p);
 
 /* Load particles from src, an FP64 planar device array [6][n] (x, y, z,

@@ -113,7 +113,7 @@ class Particles(ctypes.Structure):
         ("dtype", ctypes.c_int32),
         ("aosoa_w", ctypes.c_int32),
         ("block", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("stage", ctypes.c_int32),
         ("pad_", ctypes.c_int32),
         ("slots", ctypes.c_int64),
         ("bytes", ctypes.c_int64),
@@ -428,12 +428,14 @@ def make_force2d_grid(n, dtype=F64, layout=SOA, bc=(TRANSMISSIVE,) * 2, aosoa_w=
     return ripple_force2d_grid_init(g)
 
 
-def make_particles(n, dtype=F32, layout=SOA, aosoa_w=0, block=0):
-    """A ripple_particles descriptor with slots and bytes filled."""
+def make_particles(n, dtype=F32, layout=SOA, aosoa_w=0, block=0, stage=0):
+    """A ripple_particles descriptor with slots and bytes filled (stage 1:
+    staged through LDS)."""
     p = Particles()
     p.n = int(n)
     p.layout = int(layout)
     p.dtype = int(dtype)
     p.aosoa_w = int(aosoa_w)
     p.block = int(block)
+    p.stage = int(stage)
     return ripple_particles_init(p)

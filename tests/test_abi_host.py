@@ -238,7 +238,7 @@ def test_particles_descriptor():
 
 @pytest.mark.parametrize("bad", [
     dict(n=0), dict(n=(1 << 34) + 1), dict(dtype=2), dict(layout=3), dict(layout=R.SOA, aosoa_w=16),
-    dict(layout=R.AOSOA, aosoa_w=8), dict(block=96),
+    dict(layout=R.AOSOA, aosoa_w=8), dict(block=96), dict(stage=2), dict(stage=-1),
 ])
 def test_particles_rejects(bad):
     kw = dict(n=100)

@@ -51,11 +51,12 @@ def tol(ref, P, dt, dtype):
     return np.spacing(r).astype(np.float64) + np.spacing(np.abs(P[3:] * dt))
 
 
+@pytest.mark.parametrize("stage", [0, 1], ids=["registers", "lds"])
 @pytest.mark.parametrize("dtype", [R.F32, R.F64], ids=["f32", "f64"])
 @pytest.mark.parametrize("layout,w", LAYOUTS, ids=LAYOUT_IDS)
-def test_parity(dtype, layout, w):
-    for n in (1, 2, 3, 5, 63, 64, 65, 1000, 4097, 100003):
-        p = R.make_particles(n, dtype=dtype, layout=layout, aosoa_w=w)
+def test_parity(dtype, layout, w, stage):
+    for n in (1, 2, 3, 5, 63, 64, 65, 127, 128, 129, 255, 256, 257, 1000, 4097, 100003):
+        p = R.make_particles(n, dtype=dtype, layout=layout, aosoa_w=w, stage=stage)
         buf = load(p, state(n, n))
         P = export(p, buf)                      # the stored, rounded inputs
         dt = 1e-3 * (1 + n % 7)
@@ -73,22 +74,23 @@ def test_layouts_and_blocks_bitwise_equal(dtype):
     P = state(n, 1)
     ref = None
     for layout, w in LAYOUTS:
-        for block in (0, 64, 1024):
-            p = R.make_particles(n, dtype=dtype, layout=layout, aosoa_w=w, block=block)
+        for block, stage in ((0, 0), (64, 0), (1024, 0), (0, 1), (64, 1), (512, 1), (1024, 1)):
+            p = R.make_particles(n, dtype=dtype, layout=layout, aosoa_w=w, block=block, stage=stage)
             buf = load(p, P)
             for _ in range(3):
                 R.ripple_particles_update(G.ctx(), p, buf.data_ptr(), 0.01, G.stream())
             got = export(p, buf)
             if ref is None:
                 ref = got
-            assert np.array_equal(got, ref), (layout, w, block)
+            assert np.array_equal(got, ref), (layout, w, block, stage)
 
 
-def test_zero_dt_and_padding_slots_untouched():
+@pytest.mark.parametrize("stage", [0, 1], ids=["registers", "lds"])
+def test_zero_dt_and_padding_slots_untouched(stage):
     for dtype, view in ((R.F32, torch.int32), (R.F64, torch.int64)):
         for layout, w in LAYOUTS:
             n = 1000
-            p = R.make_particles(n, dtype=dtype, layout=layout, aosoa_w=w)
+            p = R.make_particles(n, dtype=dtype, layout=layout, aosoa_w=w, stage=stage)
             buf = torch.empty(p.bytes, dtype=torch.uint8, device="cuda")
             buf.view(view).fill_(-1)
             src = torch.as_tensor(state(n, 2), dtype=torch.float64).to("cuda").contiguous()
@@ -120,13 +122,13 @@ def test_rejected_arguments():
 
 @pytest.mark.parametrize("dtype", [R.F32, R.F64], ids=["f32", "f64"])
 def test_full_size_80M(dtype):
-    """80 million particles (the paper's largest size), SoA and AoS, every
-    particle against the oracle."""
+    """80 million particles (the paper's largest size), SoA and AoS, through
+    registers and staged through LDS, every particle against the oracle."""
     n = 80_000_000
     rng = torch.Generator(device="cuda").manual_seed(4)
     src = torch.rand((6, n), dtype=torch.float64, device="cuda", generator=rng) * 2 - 1
-    for layout in (R.SOA, R.AOS):
-        p = R.make_particles(n, dtype=dtype, layout=layout)
+    for layout, stage in ((R.SOA, 0), (R.AOS, 0), (R.SOA, 1), (R.AOS, 1)):
+        p = R.make_particles(n, dtype=dtype, layout=layout, stage=stage)
         buf = torch.empty(p.bytes, dtype=torch.uint8, device="cuda")
         R.ripple_particles_import(G.ctx(), p, src.data_ptr(), buf.data_ptr(), G.stream())
         P = export(p, buf)
@@ -135,6 +137,6 @@ def test_full_size_80M(dtype):
         dt_w = float(np.float32(0.002)) if dtype == R.F32 else 0.002
         ref = O.update(P, dt_w)
         assert np.array_equal(got[3:], P[3:])
-        assert (np.abs(got[:3] - ref[:3]) <= tol(ref, P, dt_w, dtype)).all(), layout
+        assert (np.abs(got[:3] - ref[:3]) <= tol(ref, P, dt_w, dtype)).all(), (layout, stage)
         del buf
         torch.cuda.empty_cache()
