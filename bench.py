@@ -397,7 +397,10 @@ def run_particle_workload(sizes, dtypes, layouts, reps, warmup):
 PAPER_FLUX_MS = {"soa": {1024: 0.0757, 2048: 0.2438, 4096: 0.9101, 8192: 3.5533,
                          16384: 14.282, 32768: 59.028},
                  "aos": {1024: 0.1065, 2048: 0.3614, 4096: 1.3971, 8192: 5.5284,
-                         16384: 22.081, 32768: 86.756}}
+                         16384: 22.081, 32768: 86.756},
+                 # strided layout in shared memory
+                 "soa_lds": {1024: 0.0921, 2048: 0.2979, 4096: 1.1425, 8192: 4.4941,
+                             16384: 18.090, 32768: 74.797}}
 # Arithmetic of one cell of the 2D flux difference, counted like the sweeps'
 # (each face flux is evaluated once and shared by its two cells): physical
 # x and y fluxes of the cell 19, one x and one y FORCE face 2 x 62, the two
@@ -417,7 +420,10 @@ def run_force2d_workload(sizes, dtypes, layouts, reps, warmup):
 
     ctx = R.ripple_fv_create(0)
     stream = torch.cuda.current_stream()
-    lays = {"soa": (R.SOA, 0), "aos": (R.AOS, 0), "aosoa64": (R.AOSOA, 64)}
+    # name: (layout, aosoa_w, stage); "_lds": rows staged through LDS with
+    # direct global-to-LDS loads
+    lays = {"soa": (R.SOA, 0, 0), "aos": (R.AOS, 0, 0), "aosoa64": (R.AOSOA, 64, 0),
+            "soa_lds": (R.SOA, 0, 1), "aos_lds": (R.AOS, 0, 1)}
     lam = 0.25
     rows = []
     try:
@@ -427,7 +433,8 @@ def run_force2d_workload(sizes, dtypes, layouts, reps, warmup):
             for lay_name in layouts:
                 for n in sizes:
                     g = R.make_force2d_grid((n, n), dtype=dtype, layout=lays[lay_name][0],
-                                            aosoa_w=lays[lay_name][1], bc=(R.PERIODIC,) * 2)
+                                            aosoa_w=lays[lay_name][1], bc=(R.PERIODIC,) * 2,
+                                            stage=lays[lay_name][2])
                     u = torch.empty(g.bytes, dtype=torch.uint8, device="cuda")
                     d = torch.empty(g.bytes, dtype=torch.uint8, device="cuda")
                     W = ist.smooth_periodic_2d((n, n), 2104, device="cuda")
@@ -600,7 +607,7 @@ def main():
     ap.add_argument("--force2d-only", action="store_true",
                     help="run only the 2D FORCE flux-difference leg (prints its JSON)")
     ap.add_argument("--force2d-sizes", default="1024,2048,4096,8192,16384,32768")
-    ap.add_argument("--force2d-layouts", default="soa,aos")
+    ap.add_argument("--force2d-layouts", default="soa,aos,soa_lds")
     ap.add_argument("--force2d-dtypes", default="f32,f64")
     ap.add_argument("--no-shock-bubble", action="store_true",
                     help="skip the 2D shock-bubble solver leg")

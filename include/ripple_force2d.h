@@ -54,7 +54,12 @@ extern "C" {
  *           changes results
  *  segment  rows each wave advances along y (>= 1; 0 = 8); never changes
  *           results
- *  reserved must be 0
+ *  stage    0: each wave loads its rows into registers and exchanges x
+ *           neighbours by lane shifts; 1: each wave stages its rows through
+ *           LDS with direct global-to-LDS loads and reads its x neighbour's
+ *           state there (the paper's shared-memory variant, "ss" of table
+ *           "tab:flux"; at most 512 threads per workgroup, larger blocks run
+ *           as 512); never changes results
  *  x_origin, pitch, bytes   OUT, see below
  *
  * Storage of one buffer.  Cell (i, j), each index in [-1, n] (interior plus
@@ -78,7 +83,7 @@ typedef struct ripple_force2d_grid {
   int32_t aosoa_w;
   int32_t block;
   int32_t segment;
-  int32_t reserved;
+  int32_t stage;
   int32_t x_origin;
   int32_t pad_;
   int64_t pitch[2];
@@ -86,8 +91,8 @@ typedef struct ripple_force2d_grid {
 } ripple_force2d_grid;
 
 /* Validate a descriptor and fill x_origin, pitch[] and bytes.  E_INVALID on
- * extents < 1 or above 2^20, unknown enums, bad aosoa_w or tiling knobs, a
- * nonzero reserved field, or a buffer above 2^46 bytes. */
+ * extents < 1 or above 2^20, unknown enums, bad aosoa_w, tiling knobs or
+ * stage, or a buffer above 2^46 bytes. */
 ripple_fv_status ripple_force2d_grid_init(ripple_force2d_grid* g);
 
 /* Load a state.  src: FP64 planar device array [4][n1][n0] (interior), or

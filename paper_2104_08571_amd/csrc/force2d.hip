@@ -104,6 +104,16 @@ __device__ __forceinline__ void store_row(void* buf, int64_t q0, int64_t ctot, u
   }
 }
 
+// Four consecutive FP32 values as one 16-byte LDS read.
+__device__ __forceinline__ void ldv4(const float* p, float u[4]) {
+  using V = float __attribute__((ext_vector_type(4)));
+  const V v = *reinterpret_cast<const V*>(p);
+  u[0] = v[0];
+  u[1] = v[1];
+  u[2] = v[2];
+  u[3] = v[3];
+}
+
 // Physical fluxes of one state along x (F) and y (G), sharing 1/rho and p:
 //   F = (m_x, m_x u + p, m_y u, u (E + p)),  G = (m_y, m_x v, m_y v + p, v (E + p)),
 //   p = (gamma - 1) E - ((gamma - 1)/2) |m|^2 / rho.
@@ -252,6 +262,153 @@ __global__ void __launch_bounds__(F2_MAX_BLOCK) k_force2d(F2Params p) {
   if (j + 1 < j1) row(r1, r2, r0, j + 1);
 }
 
+// The same tiles with the rows staged through LDS (the paper's strided
+// shared-memory variant, table "tab:flux", and its contiguous counterpart):
+// each wave copies every row it needs into a ring of three row slots in its
+// own LDS region with direct global-to-LDS loads (the data bypasses the
+// vector registers; lane l of a 4-byte load fills bytes 4 l .. 4 l + 3 of
+// the slot part, of a 16-byte load 16 l .. 16 l + 15), then reads its own
+// cell and its upper x neighbour's from there instead of loading the row
+// into registers and shifting it across lanes.  Row j + 2 is copied while
+// row j is computed.  Computed fluxes still move by lane shifts.  Waves are
+// independent: no barrier.
+//
+// Slot layout (bytes): FP32 planar, component c at 256 c (4 bytes per lane);
+// FP64 planar, the low and high words of component c at 512 c and 512 c +
+// 256; AoS FP32, the 16-byte cells at 0; AoS FP64, the two halves of the
+// 32-byte cells at 0 and 1024.
+template <typename T> constexpr int f2_slot_bytes() { return sizeof(T) == 4 ? 1024 : 2048; }
+constexpr int F2_STAGE_MAX_BLOCK = 512;   // 3 slots x 8 waves: at most 48 KB of LDS
+
+using f2_lds_ptr = __attribute__((address_space(3))) void*;
+
+template <int BYTES>
+__device__ __forceinline__ void f2_copy_to_lds(const void* src, unsigned char* dst) {
+  static_assert(BYTES == 4 || BYTES == 16, "4- or 16-byte loads");
+  if constexpr (BYTES == 4) __builtin_amdgcn_global_load_lds(src, (f2_lds_ptr)dst, 4, 0, 0);
+  else __builtin_amdgcn_global_load_lds(src, (f2_lds_ptr)dst, 16, 0, 0);
+}
+
+template <typename T, int LAY>
+__global__ void __launch_bounds__(F2_STAGE_MAX_BLOCK) k_force2d_lds(F2Params p) {
+  using L = Layout4<LAY>;
+  extern __shared__ __attribute__((aligned(16))) unsigned char f2_lds[];
+  constexpr int SB = f2_slot_bytes<T>();
+  const int lane = threadIdx.x & 63;
+  const int64_t t = uniform(xcd_order(blockIdx.x, gridDim.x) * (int64_t)(blockDim.x >> 6) +
+                            (int64_t)(threadIdx.x >> 6));
+  if (t >= p.ntiles) return;
+  unsigned char* region = f2_lds + (threadIdx.x >> 6) * 3 * SB;
+  const int strip = (int)(t % p.nstrip);
+  const int sg = (int)(t / p.nstrip);
+  const int nx = p.nx, ny = p.ny;
+  const int col = strip * F2_OUT - 1 + lane;
+  const int mc = face_index(min(col, nx), nx, p.mode[0], p.mode[1]);
+  const bool out = lane >= 1 && lane <= F2_OUT && col < nx;
+  const uint32_t ld = L::rel((uint32_t)(mc + p.ox)) * (uint32_t)sizeof(T);
+  const uint32_t st = L::rel((uint32_t)(min(col, nx) + p.ox)) * (uint32_t)sizeof(T);
+  const int mylo = p.mode[2], myhi = p.mode[3];
+  const int64_t px = p.px, ctot = p.ctot;
+  const T hinv_x = (T)p.hinv_x, hl_x = (T)p.hl_x;
+  const T hinv_y = (T)p.hinv_y, hl_y = (T)p.hl_y;
+  const int j0 = sg * p.seg;
+  const int j1 = min(j0 + p.seg, ny);
+  auto row_q = [&](int j) -> int64_t {
+    return (int64_t)(face_index(j, ny, mylo, myhi) + 1) * px;
+  };
+  // slot of row j: rows j0 - 1, j0, j0 + 1, j0 + 2, ... take slots 0, 1, 2, 0, ...
+  auto slot = [&](int j) -> unsigned char* { return region + ((j - j0 + 1) % 3) * SB; };
+  auto copy_row = [&](int j) {
+    unsigned char* dst = slot(j);
+    const int64_t q0 = row_q(j);
+    if constexpr (LAY == LAY_AOS) {
+      const unsigned char* src =
+          static_cast<const unsigned char*>(p.u) + q0 * NV2 * (int64_t)sizeof(T) + ld;
+      f2_copy_to_lds<16>(src, dst);
+      if constexpr (sizeof(T) == 8) f2_copy_to_lds<16>(src + 16, dst + 1024);
+    } else {
+#pragma unroll
+      for (int c = 0; c < NV2; ++c) {
+        const unsigned char* src =
+            reinterpret_cast<const unsigned char*>(static_cast<const T*>(p.u) + L::off(q0, c, ctot)) + ld;
+        if constexpr (sizeof(T) == 4) {
+          f2_copy_to_lds<4>(src, dst + 256 * c);
+        } else {
+          f2_copy_to_lds<4>(src, dst + 512 * c);
+          f2_copy_to_lds<4>(src + 4, dst + 512 * c + 256);
+        }
+      }
+    }
+  };
+  // the state of lane k's cell in the row held by slot s
+  auto read_cell = [&](const unsigned char* s, int k, T u[NV2]) {
+    if constexpr (LAY == LAY_AOS) {
+      if constexpr (sizeof(T) == 4) {
+        ldv4(reinterpret_cast<const float*>(s + 16 * k), u);
+      } else {
+        const double* a = reinterpret_cast<const double*>(s + 16 * k);
+        const double* b = reinterpret_cast<const double*>(s + 1024 + 16 * k);
+        u[0] = a[0];
+        u[1] = a[1];
+        u[2] = b[0];
+        u[3] = b[1];
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < NV2; ++c) {
+        if constexpr (sizeof(T) == 4) {
+          u[c] = reinterpret_cast<const float*>(s + 256 * c)[k];
+        } else {
+          const uint32_t lo = reinterpret_cast<const uint32_t*>(s + 512 * c)[k];
+          const uint32_t hi = reinterpret_cast<const uint32_t*>(s + 512 * c + 256)[k];
+          u[c] = __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+        }
+      }
+    }
+  };
+  const int east = min(lane + 1, 63);
+
+  T uc[NV2], Fc[NV2], Gc[NV2], gprev[NV2];
+  {
+    copy_row(j0 - 1);
+    copy_row(j0);
+    copy_row(j0 + 1);                           // j0 + 1 <= j1 always
+    __builtin_amdgcn_s_waitcnt(0);
+    T um[NV2], Fm[NV2], Gm[NV2];
+    read_cell(slot(j0 - 1), lane, um);
+    read_cell(slot(j0), lane, uc);
+    phys_fluxes(um, Fm, Gm);
+    phys_fluxes(uc, Fc, Gc);
+    force_face<T, 1>(um, uc, Gm, Gc, hinv_y, hl_y, gprev);
+  }
+  for (int j = j0; j < j1; ++j) {
+    // rows j and j + 1 are in their slots; copy row j + 2 into the slot of
+    // row j - 1 (no longer read) while row j is computed
+    __builtin_amdgcn_s_waitcnt(0);
+    if (j + 2 <= j1) copy_row(j + 2);
+    T un[NV2], ur[NV2], fr[NV2], fx[NV2];
+    read_cell(slot(j + 1), lane, un);
+    read_cell(slot(j), east, ur);
+#pragma unroll
+    for (int c = 0; c < NV2; ++c) fr[c] = from_above(Fc[c]);
+    force_face<T, 0>(uc, ur, Fc, fr, hinv_x, hl_x, fx);
+    T Fn[NV2], Gn[NV2], gy[NV2];
+    phys_fluxes(un, Fn, Gn);
+    force_face<T, 1>(uc, un, Gc, Gn, hinv_y, hl_y, gy);
+    T dd[NV2];
+#pragma unroll
+    for (int c = 0; c < NV2; ++c) dd[c] = (fx[c] - from_below(fx[c])) + (gy[c] - gprev[c]);
+    if (out) store_row<T, LAY>(p.d, (int64_t)(j + 1) * px, ctot, st, dd);
+#pragma unroll
+    for (int c = 0; c < NV2; ++c) {
+      uc[c] = un[c];
+      Fc[c] = Fn[c];
+      Gc[c] = Gn[c];
+      gprev[c] = gy[c];
+    }
+  }
+}
+
 // Transfers between FP64 planar arrays and the padded storage (not timed).
 struct D2 {
   void* buf;
@@ -336,21 +493,26 @@ int transfer_blocks(int64_t ncell) {
 int f2_segment(const ripple_force2d_grid& g) { return g.segment > 0 ? g.segment : 8; }
 
 template <typename T, int LAY>
-hipError_t launch_force2d_typed(const F2Params& p, int block, hipStream_t s) {
+hipError_t launch_force2d_typed(const F2Params& p, int block, int stage, hipStream_t s) {
+  if (stage) block = std::min(block, F2_STAGE_MAX_BLOCK);
   const int wpb = block / 64;
   const int64_t blocks = (p.ntiles + wpb - 1) / wpb;
-  hipLaunchKernelGGL((k_force2d<T, LAY>), dim3((unsigned)blocks), dim3(block), 0, s, p);
+  if (stage)
+    hipLaunchKernelGGL((k_force2d_lds<T, LAY>), dim3((unsigned)blocks), dim3(block),
+                       wpb * 3 * f2_slot_bytes<T>(), s, p);
+  else
+    hipLaunchKernelGGL((k_force2d<T, LAY>), dim3((unsigned)blocks), dim3(block), 0, s, p);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_force2d_dtype(int lay, const F2Params& p, int block, hipStream_t s) {
+hipError_t launch_force2d_dtype(int lay, const F2Params& p, int block, int stage, hipStream_t s) {
   switch (lay) {
-    case LAY_AOS: return launch_force2d_typed<T, LAY_AOS>(p, block, s);
-    case LAY_SOA: return launch_force2d_typed<T, LAY_SOA>(p, block, s);
-    case LAY_AOSOA16: return launch_force2d_typed<T, LAY_AOSOA16>(p, block, s);
-    case LAY_AOSOA32: return launch_force2d_typed<T, LAY_AOSOA32>(p, block, s);
-    default: return launch_force2d_typed<T, LAY_AOSOA64>(p, block, s);
+    case LAY_AOS: return launch_force2d_typed<T, LAY_AOS>(p, block, stage, s);
+    case LAY_SOA: return launch_force2d_typed<T, LAY_SOA>(p, block, stage, s);
+    case LAY_AOSOA16: return launch_force2d_typed<T, LAY_AOSOA16>(p, block, stage, s);
+    case LAY_AOSOA32: return launch_force2d_typed<T, LAY_AOSOA32>(p, block, stage, s);
+    default: return launch_force2d_typed<T, LAY_AOSOA64>(p, block, stage, s);
   }
 }
 
@@ -377,7 +539,7 @@ const char* grid2_invalid(const ripple_force2d_grid& g) {
       g.block != 1024)
     return "block must be 0, 64, 128, 256, 512 or 1024";
   if (g.segment < 0) return "segment < 0";
-  if (g.reserved != 0) return "reserved must be 0";
+  if (g.stage != 0 && g.stage != 1) return "stage must be 0 or 1";
   return nullptr;
 }
 
@@ -519,8 +681,8 @@ ripple_fv_status ripple_force2d_flux_difference(ripple_fv_ctx* ctx, const ripple
   const int block = g->block ? g->block : 256;
   const int lay = lay_of2(*g);
   const hipError_t e = g->dtype == RIPPLE_FV_F32
-                           ? launch_force2d_dtype<float>(lay, p, block, (hipStream_t)stream)
-                           : launch_force2d_dtype<double>(lay, p, block, (hipStream_t)stream);
+                           ? launch_force2d_dtype<float>(lay, p, block, g->stage, (hipStream_t)stream)
+                           : launch_force2d_dtype<double>(lay, p, block, g->stage, (hipStream_t)stream);
   if (e != hipSuccess) return ctx_fail(ctx, RIPPLE_FV_E_DEVICE, hipGetErrorString(e));
   return RIPPLE_FV_OK;
 }

@@ -92,7 +92,7 @@ class Force2DGrid(ctypes.Structure):
         ("aosoa_w", ctypes.c_int32),
         ("block", ctypes.c_int32),
         ("segment", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("stage", ctypes.c_int32),
         ("x_origin", ctypes.c_int32),
         ("pad_", ctypes.c_int32),
         ("pitch", ctypes.c_int64 * 2),
@@ -414,8 +414,9 @@ def copy_grid(g, **changes):
 
 
 def make_force2d_grid(n, dtype=F64, layout=SOA, bc=(TRANSMISSIVE,) * 2, aosoa_w=0, block=0,
-                      segment=0):
-    """A ripple_force2d_grid with x_origin, pitch and bytes filled."""
+                      segment=0, stage=0):
+    """A ripple_force2d_grid with x_origin, pitch and bytes filled (stage 1:
+    rows staged through LDS)."""
     g = Force2DGrid()
     for d in range(2):
         g.n[d] = int(n[d])
@@ -425,6 +426,7 @@ def make_force2d_grid(n, dtype=F64, layout=SOA, bc=(TRANSMISSIVE,) * 2, aosoa_w=
     g.aosoa_w = int(aosoa_w)
     g.block = int(block)
     g.segment = int(segment)
+    g.stage = int(stage)
     return ripple_force2d_grid_init(g)
 
 

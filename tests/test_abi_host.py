@@ -218,12 +218,13 @@ def test_force2d_grid_init_rejects(bad):
     assert e.value.status == R.E_INVALID
 
 
-def test_force2d_reserved_must_be_zero():
+@pytest.mark.parametrize("stage,status", [(0, R.OK), (1, R.OK), (2, R.E_INVALID), (-1, R.E_INVALID)])
+def test_force2d_stage_values(stage, status):
     g = R.Force2DGrid()
     g.n[0] = g.n[1] = 8
     g.layout = R.SOA
-    g.reserved = 1
-    assert R.call("ripple_force2d_grid_init", ctypes.byref(g)) == R.E_INVALID
+    g.stage = stage
+    assert R.call("ripple_force2d_grid_init", ctypes.byref(g)) == status
 
 
 # -- particle descriptors ------------------------------------------------------------

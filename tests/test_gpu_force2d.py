@@ -86,15 +86,18 @@ SHAPES = [(1, 1), (2, 1), (1, 5), (3, 2), (61, 3), (62, 17), (63, 33), (64, 16),
           (125, 129)]
 
 
+@pytest.mark.parametrize("stage", [0, 1], ids=["registers", "lds"])
 @pytest.mark.parametrize("dtype", [R.F32, R.F64], ids=["f32", "f64"])
 @pytest.mark.parametrize("layout,w", LAYOUTS, ids=LAYOUT_IDS)
-def test_parity_random_states(dtype, layout, w):
+def test_parity_random_states(dtype, layout, w, stage):
     """Cell-wise random states, every boundary combination, grids from one
-    cell to several strips (62 columns) and segments with ragged ends."""
+    cell to several strips (62 columns) and segments with ragged ends; rows
+    through registers and staged through LDS."""
     lam = (0.3, 0.2)
     for k, shape in enumerate(SHAPES):
         for bc in ((0, 0), (1, 1), (0, 1), (1, 0)):
-            g = R.make_force2d_grid(shape, dtype=dtype, layout=layout, aosoa_w=w, bc=bc)
+            g = R.make_force2d_grid(shape, dtype=dtype, layout=layout, aosoa_w=w, bc=bc,
+                                    stage=stage)
             u = load(g, random_state(shape, 100 + k))
             U = export(g, u)
             D = export(g, flux_difference(g, u, lam))
@@ -150,18 +153,21 @@ def test_uniform_state_gives_zero(dtype):
 
 @pytest.mark.parametrize("dtype", [R.F32, R.F64], ids=["f32", "f64"])
 def test_layouts_and_tilings_bitwise_equal(dtype):
-    """Layout, workgroup size and segment length never change the bits."""
+    """Layout, workgroup size, segment length and LDS staging never change
+    the bits."""
     shape, lam, bc = (150, 77), (0.3, 0.2), (1, 0)
     W = random_state(shape, 7)
     ref = None
     for layout, w in LAYOUTS:
-        for block, seg in ((0, 0), (64, 1), (128, 2), (256, 3), (512, 5), (64, 16), (512, 200)):
+        for block, seg, stage in ((0, 0, 0), (64, 1, 0), (128, 2, 0), (256, 3, 0), (512, 5, 0),
+                                  (64, 16, 0), (512, 200, 0), (0, 0, 1), (64, 1, 1), (256, 3, 1),
+                                  (1024, 16, 1), (512, 200, 1)):
             g = R.make_force2d_grid(shape, dtype=dtype, layout=layout, aosoa_w=w, bc=bc,
-                                    block=block, segment=seg)
+                                    block=block, segment=seg, stage=stage)
             D = export(g, flux_difference(g, load(g, W), lam))
             if ref is None:
                 ref = D
-            assert np.array_equal(D, ref), (layout, w, block, seg)
+            assert np.array_equal(D, ref), (layout, w, block, seg, stage)
 
 
 @pytest.mark.parametrize("dtype", [R.F32, R.F64], ids=["f32", "f64"])
@@ -180,16 +186,18 @@ def test_padded_boundary_reads_storage(dtype):
         ref_g = R.make_force2d_grid(shape, dtype=dtype, layout=R.SOA, bc=bc)
         ref = export(ref_g, flux_difference(ref_g, load(ref_g, W), lam))
         for padded in ((2, 2), (2, bc[1]), (bc[0], 2)):
-            g = R.make_force2d_grid(shape, dtype=dtype, layout=R.AOS, bc=padded)
-            u = load(g, P, variables=R.PRIMITIVE | R.WITH_PADDING)
-            D = export(g, flux_difference(g, u, lam))
-            assert np.array_equal(D, ref), (bc, padded)
+            for layout, stage in ((R.AOS, 0), (R.AOS, 1), (R.SOA, 1)):
+                g = R.make_force2d_grid(shape, dtype=dtype, layout=layout, bc=padded, stage=stage)
+                u = load(g, P, variables=R.PRIMITIVE | R.WITH_PADDING)
+                D = export(g, flux_difference(g, u, lam))
+                assert np.array_equal(D, ref), (bc, padded, layout, stage)
 
 
-def test_output_padding_and_input_untouched():
+@pytest.mark.parametrize("stage", [0, 1], ids=["registers", "lds"])
+def test_output_padding_and_input_untouched(stage):
     shape = (100, 40)
     for dtype, view in ((R.F32, torch.int32), (R.F64, torch.int64)):
-        g = R.make_force2d_grid(shape, dtype=dtype, layout=R.SOA, bc=(0, 1))
+        g = R.make_force2d_grid(shape, dtype=dtype, layout=R.SOA, bc=(0, 1), stage=stage)
         u = load(g, random_state(shape, 9))
         before = u.clone()
         d = torch.empty(g.bytes, dtype=torch.uint8, device="cuda")
@@ -247,15 +255,17 @@ def window(U_dev, bc, cells):
     return out
 
 
+@pytest.mark.parametrize("stage", [0, 1], ids=["registers", "lds"])
 @pytest.mark.parametrize("dtype", [R.F32, R.F64], ids=["f32", "f64"])
-def test_full_size_sampled(dtype):
+def test_full_size_sampled(dtype, stage):
     """32768^2 (the largest size of the paper's table) smooth periodic field,
-    SoA, in the benchmark's launch configuration: sampled cells -- corners,
-    edges, strip and segment boundaries, random interior cells -- against
-    the oracle on their neighbourhoods; the periodic sum of the flux
-    differences vanishes to rounding."""
+    SoA, in the benchmark's launch configurations (rows through registers
+    and staged through LDS): sampled cells -- corners, edges, strip and
+    segment boundaries, random interior cells -- against the oracle on their
+    neighbourhoods; the periodic sum of the flux differences vanishes to
+    rounding."""
     n, lam = 32768, (0.25, 0.25)
-    g = R.make_force2d_grid((n, n), dtype=dtype, layout=R.SOA, bc=(1, 1))
+    g = R.make_force2d_grid((n, n), dtype=dtype, layout=R.SOA, bc=(1, 1), stage=stage)
     W = ist.smooth_periodic_2d((n, n), 8571, device="cuda")
     u = buffer(g)
     R.ripple_force2d_import(G.ctx(), g, W.data_ptr(), R.PRIMITIVE, u.data_ptr(), G.stream())
