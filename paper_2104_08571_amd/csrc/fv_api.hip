@@ -271,14 +271,16 @@ ripple_fv_status grid_check(const ripple_fv_grid* g, int64_t pitch[3], int64_t* 
   if (b > MAX_BYTES) { *why = "grid too large"; return RIPPLE_FV_E_INVALID; }
   // Per-lane byte offsets from a tile's wave-uniform base are 32-bit buffer
   // offsets.  The tiles that span the most memory are the rows form of the
-  // fused x-y pass (up to XY_THREADS / n0 rows at consecutive z) and the
-  // separate y sweep (lanes across x, then z: up to 2 * 256 / n0 + 1
-  // planes); every other tile stays within a few rows.  Bound the largest
-  // span generously by 2 * XY_THREADS / n0 + 2 planes (at most n2): that
-  // many plane pitches plus a row pitch and the alignment slack, times the
-  // cells' element stride (5 in AoS and AoSoA).
+  // fused x-y pass (up to XY_THREADS / n0 rows at consecutive z), the waves
+  // of the strips form that share the tails of up to RFV_STRIP_KMAX rows at
+  // consecutive z, and the separate y sweep (lanes across x, then z: up to 2
+  // * 256 / n0 + 1 planes); every other tile stays within a few rows.  Bound
+  // the largest span generously by max(2 * XY_THREADS / n0, RFV_STRIP_KMAX)
+  // + 2 planes (at most n2): that many plane pitches plus a row pitch and the
+  // alignment slack, times the cells' element stride (5 in AoS and AoSoA).
   {
-    const int64_t planes = std::min<int64_t>(g->n[2], 2 * XY_THREADS / g->n[0] + 2);
+    const int64_t planes = std::min<int64_t>(
+        g->n[2], std::max<int64_t>(2 * XY_THREADS / g->n[0], RFV_STRIP_KMAX) + 2);
     const int64_t span_cells = (planes - 1) * px * py + px + ox + 64;
     const int64_t stride = g->layout == RIPPLE_FV_SOA ? 1 : 5;
     if (span_cells * stride * elem >= (int64_t(1) << 31)) {

@@ -68,6 +68,71 @@ RFV_HD XPos x_position(int tid, int F0, int lx, int ny, int nz) {
   return r;
 }
 
+// Wave strips of the fused x-y pass: a row of nx cells takes nsx strips of
+// `cells` cells, each held by one wave with two ghost lanes on either side;
+// the last strip holds the tail of t = nx - (nsx - 1) cells cells.  When k
+// = min(64 / (t + 4), RFV_STRIP_KMAX, nz) >= 3, the tails of k consecutive
+// rows (at consecutive z) share one wave, sub-strip h taking lanes h (t + 4)
+// .. h (t + 4) + t + 3.  A group of k rows then takes per = k (nsx - 1) + 1
+// waves: its rows' full strips, row-major, then the shared tails.  A wave
+// of shared tails runs the instructions of any other wave but takes longer,
+// its loads spanning k planes: measured about 1.5 to 1.9 times a full wave
+// for k = 2 and 3, and several times for k = 4 to 8.  So two tails keep a
+// wave each (on rows of 384 cells sharing gained 1.7 % on the FP32 x-y
+// pass of a single grid, 3.9 % in FP64, and lost 1.1 % on FP32 sub-blocks
+// linked along x), and at most three share one (rows of 370 cells: 5.8 %
+// faster in FP32 and 2.6 % in FP64 with three, 3.7 and 1.8 % with four, 3.3
+// and 1.5 % with up to twelve; rows of 256 cells in FP64: 8.3 %).
+#ifndef RFV_STRIP_KMAX
+#define RFV_STRIP_KMAX 3
+#endif
+struct StripPlan {
+  int nsx;    // strips per row
+  int tail;   // cells of the last strip
+  int k;      // rows whose tails share a wave (1: no sharing)
+  int per;    // waves per group of k rows
+};
+RFV_HD StripPlan strip_plan(int nx, int nz, int cells) {
+  StripPlan s;
+  s.nsx = (nx + cells - 1) / cells;
+  s.tail = nx - (s.nsx - 1) * cells;
+  s.k = 64 / (s.tail + 4);
+  if (s.k > RFV_STRIP_KMAX) s.k = RFV_STRIP_KMAX;
+  if (s.k > nz) s.k = nz;
+  if (s.k < 3) s.k = 1;
+  s.per = s.k * (s.nsx - 1) + 1;
+  return s;
+}
+
+// The strip that wave fw (in launch order) holds, and the part of it that
+// lane `lane` takes: row kw + h (at z; kw is uniform over the wave), x from
+// xoff + lane_in - 2.  The lanes past the last sub-strip's ghost lanes join
+// that sub-strip at lane_in > ncx + 3; like the lanes past ncx + 1 of any
+// strip they hold no cell.
+struct StripLane {
+  int xoff;     // x of the strip's first cell
+  int ncx;      // cells of the strip
+  int kw;       // row of sub-strip 0
+  int h;        // sub-strip of the lane
+  int lane_in;  // lane within its sub-strip (0 .. ncx + 3 hold x - 2 .. x + 1)
+};
+RFV_HD StripLane strip_lane(const StripPlan& sp, int fw, int lane, int cells) {
+  StripLane r;
+  const int grp = fw / sp.per;
+  const int w = fw - grp * sp.per;
+  const int nfull = sp.nsx - 1;
+  const bool tailw = w >= sp.k * nfull;
+  const int q = tailw ? 0 : w / (nfull > 0 ? nfull : 1);
+  r.xoff = tailw ? nfull * cells : (w - q * nfull) * cells;
+  r.ncx = tailw ? sp.tail : cells;
+  r.kw = grp * sp.k + q;
+  int h = tailw ? lane / (sp.tail + 4) : 0;
+  if (h > sp.k - 1) h = sp.k - 1;
+  r.h = h;
+  r.lane_in = lane - h * (sp.tail + 4);
+  return r;
+}
+
 // Dispatch order of a launch over tiles of the given costs, for a part whose
 // workgroups go round-robin to nxcd XCDs (workgroup w to XCD w mod nxcd), each
 // of which starts its workgroups in index order as CUs free up.  With tiles

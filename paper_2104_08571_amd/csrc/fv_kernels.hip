@@ -483,25 +483,32 @@ __global__ void __launch_bounds__(XM == XM_WAVES ? XY_WAVE_THREADS : XY_THREADS)
     const int nseg = (ny + p.seg - 1) / p.seg;
     const int s = lt % nseg;
     const int rest = lt / nseg;
-    // XM_WAVES: wave wv takes entry rest * R + wv of the (z, strip) pairs in
-    // row-major order; XM_ROWS: the tile's R rows lie at consecutive z from
-    // rest * R.
+    // XM_WAVES: wave wv takes entry rest * R + wv of the waves of the strip
+    // plan (groups of k rows at consecutive z: their full strips row-major,
+    // then their shared tails); XM_ROWS: the tile's R rows lie at
+    // consecutive z from rest * R.
     const bool ghost_lanes = WAVES || linked_x;
     const int R = WAVES ? NT / 64 : NT / (ghost_lanes ? nx + 4 : nx);  // rows per tile
-    const int nsx = WAVES ? (nx + XY_WAVE_CELLS - 1) / XY_WAVE_CELLS : 1;  // strips per row
     const int wv = WAVES ? uniform(tid >> 6) : 0;
     const int fw = rest * R + wv;
-    const int xoff = WAVES ? (fw % nsx) * XY_WAVE_CELLS : 0;  // x of the strip's first cell
-    const int ncx = WAVES ? min(nx - xoff, XY_WAVE_CELLS) : nx;  // cells of the row or strip
+    int xoff = 0, ncx = nx, kw = 0, h = 0, lane_in = 0;
+    if constexpr (WAVES) {
+      const StripLane sl = strip_lane(strip_plan(nx, nz, XY_WAVE_CELLS), fw, (int)__lane_id(),
+                                      XY_WAVE_CELLS);
+      xoff = sl.xoff;
+      ncx = sl.ncx;
+      kw = sl.kw;
+      h = sl.h;
+      lane_in = sl.lane_in;
+    }
     const int P = WAVES ? 64 : (ghost_lanes ? nx + 4 : nx);  // lanes per row
     const int rs = WAVES ? wv : tid / P;           // row slot of this lane
-    // the lane's x relative to xoff (-2 .. ncx+1 with ghost lanes; in a wave
-    // the lanes past ncx+1 hold no cell and only feed discarded values)
-    const int xl_ = WAVES ? (int)__lane_id() - 2 : tid - rs * P - (ghost_lanes ? 2 : 0);
+    // the lane's x relative to xoff (-2 .. ncx+1 with ghost lanes)
+    const int xl_ = WAVES ? lane_in - 2 : tid - rs * P - (ghost_lanes ? 2 : 0);
     const int x = xoff + xl_;                      // ... and in the row
-    const int kk = WAVES ? fw / nsx : rest * R + rs;
+    const int kk = WAVES ? kw + h : rest * R + rs;
+    if (WAVES && kw >= nz) continue;               // (uniform over the wave)
     const bool row_on = (WAVES || rs < R) && kk < nz;  // the lane belongs to a row
-    if (WAVES && !row_on) continue;                // (uniform over the wave)
     const bool on = row_on && xl_ >= 0 && xl_ < ncx;  // ... and holds a cell
     // both x faces periodic: the ghost reconstruction and the last face are
     // those of the partner cells (any other case computes them)
@@ -513,7 +520,7 @@ __global__ void __launch_bounds__(XM == XM_WAVES ? XY_WAVE_THREADS : XY_THREADS)
     const int xr = on ? xl_ : 0;                   // slot whose neighbours it reads
     // addresses: column (x, kk) at row j is q0 + (j + 2) Px + lane offset; a
     // ghost lane reads the cell its face names (clamped, wrapped or padding)
-    const int kb = WAVES ? kk : rest * R;          // first z of the tile's rows
+    const int kb = WAVES ? kw : rest * R;          // first z of the wave's or tile's rows
     const int kc = row_on ? kk : kb;
     const int xq = WAVES ? min(x, nx + 1) : x;
     const int xc = row_on ? face_index(xq, nx, G.mode[0], G.mode[1]) : 0;
@@ -1168,7 +1175,8 @@ static double xy_wave_cost(int dtype) { return dtype == RIPPLE_FV_F64 ? 0.76 : 1
 
 int xy_mode(int dtype, const ripple_fv_grid* grids, int n, int split_xy) {
   if (split_xy == 3) return XM_WAVES;
-  // lanes occupied per cell, summed over the batch, of either form
+  // lanes occupied, summed over the batch's rows, of either form (whole
+  // tiles of R rows; whole groups of k rows sharing their tails)
   double rows = 0.0, waves = 0.0;
   for (int i = 0; i < n; ++i) {
     const ripple_fv_grid& g = grids[i];
@@ -1176,9 +1184,9 @@ int xy_mode(int dtype, const ripple_fv_grid* grids, int n, int split_xy) {
     const int P = xy_row_lanes(g);
     if (P == 0) return XM_WAVES;
     const int R = XY_THREADS / P;
-    rows += cells * XY_THREADS / ((double)R * g.n[0]);
-    const int nsx = (g.n[0] + XY_WAVE_CELLS - 1) / XY_WAVE_CELLS;
-    waves += cells * xy_wave_cost(dtype) * (64.0 * nsx) / g.n[0];
+    rows += (double)XY_THREADS * ((g.n[2] + R - 1) / R) * g.n[1];
+    const StripPlan sp = strip_plan(g.n[0], g.n[2], XY_WAVE_CELLS);
+    waves += xy_wave_cost(dtype) * 64.0 * sp.per * ((g.n[2] + sp.k - 1) / sp.k) * g.n[1];
   }
   return split_xy == 0 && waves < rows ? XM_WAVES : XM_ROWS;
 }
@@ -1186,9 +1194,10 @@ int xy_mode(int dtype, const ripple_fv_grid* grids, int n, int split_xy) {
 int64_t tiles_xy(const ripple_fv_grid& g, int yz_segment, int xmode) {
   const int64_t nseg = (g.n[1] + yz_segment - 1) / yz_segment;
   if (xmode == XM_WAVES) {
-    const int64_t nsx = (g.n[0] + XY_WAVE_CELLS - 1) / XY_WAVE_CELLS;
+    const StripPlan sp = strip_plan(g.n[0], g.n[2], XY_WAVE_CELLS);
+    const int64_t items = (int64_t)(g.n[2] + sp.k - 1) / sp.k * sp.per;
     const int64_t waves = XY_WAVE_THREADS / 64;
-    return (g.n[2] * nsx + waves - 1) / waves * nseg;
+    return (items + waves - 1) / waves * nseg;
   }
   const int64_t rows = XY_THREADS / xy_row_lanes(g);
   return (g.n[2] + rows - 1) / rows * nseg;

@@ -1,6 +1,7 @@
 // Host check of the sweeps' index arithmetic (fv_index.hpp) against its plain
-// definition: divisions of the flattened position; and of the launches'
-// dispatch orders against the properties that define them.  Prints "ok" or
+// definition: divisions of the flattened position, the wave strips' lane
+// map; and of the launches' dispatch orders against the properties that
+// define them.  Prints "ok" or
 // the first mismatch and exits non-zero.
 #include <cstdint>
 #include <cstdio>
@@ -130,9 +131,56 @@ static int check_orders() {
   return 0;
 }
 
+// Wave strips: over the waves that cover a grid's rows (groups of the strip
+// plan, rounded up to whole workgroups of `wpt` waves), every cell (x, z) of
+// the nx x nz rows is held by exactly one lane, and the four lanes around
+// it hold x - 2 .. x + 2 of the same row (so the lane shifts read the
+// stencil); no wave spans more than 12 rows past its first.
+static int check_strips(int nx, int nz, int cells, int wpt) {
+  const StripPlan sp = strip_plan(nx, nz, cells);
+  const int64_t items = (int64_t)(nz + sp.k - 1) / sp.k * sp.per;
+  const int64_t waves = (items + wpt - 1) / wpt * wpt;
+  std::vector<int> seen((size_t)nx * nz, 0);
+  for (int fw = 0; fw < waves; ++fw) {
+    StripLane l[64];
+    for (int ln = 0; ln < 64; ++ln) l[ln] = strip_lane(sp, fw, ln, cells);
+    if (l[0].kw >= nz) continue;
+    for (int ln = 0; ln < 64; ++ln) {
+      const int kk = l[ln].kw + l[ln].h, xl = l[ln].lane_in - 2;
+      if (l[ln].kw != l[0].kw || l[ln].h > 11) {
+        std::printf("strips nx=%d nz=%d: wave %d lane %d row %d\n", nx, nz, fw, ln, kk);
+        return 1;
+      }
+      if (kk >= nz || xl < 0 || xl >= l[ln].ncx) continue;
+      const int x = l[ln].xoff + xl;
+      if (x >= nx || ++seen[(size_t)kk * nx + x] != 1) {
+        std::printf("strips nx=%d nz=%d: cell (%d, %d) again at wave %d\n", nx, nz, x, kk, fw);
+        return 1;
+      }
+      for (int d = -2; d <= 2; ++d) {
+        const int m = ln + d;
+        if (m < 0 || m > 63 || l[m].kw + l[m].h != kk || l[m].xoff + l[m].lane_in - 2 != x + d) {
+          std::printf("strips nx=%d nz=%d: lane %d of wave %d, neighbour %d\n", nx, nz, ln, fw, d);
+          return 1;
+        }
+      }
+    }
+  }
+  for (size_t i = 0; i < seen.size(); ++i)
+    if (seen[i] != 1) {
+      std::printf("strips nx=%d nz=%d: cell %zu not held\n", nx, nz, i);
+      return 1;
+    }
+  return 0;
+}
+
 int main() {
   if (check_face()) return 1;
   if (check_orders()) return 1;
+  for (int nx : {1, 2, 5, 24, 28, 29, 59, 60, 61, 64, 80, 120, 121, 150, 256, 384, 385, 512, 1000})
+    for (int nz : {1, 2, 3, 5, 12, 13, 25})
+      for (int wpt : {1, 4})
+        if (check_strips(nx, nz, 60, wpt)) return 1;
   const int nxs[] = {1, 2, 3, 5, 17, 32, 61, 124, 125, 252, 253, 256, 300, 512};
   const int nys[] = {1, 3, 7, 16};
   const int nzs[] = {1, 2, 5};

@@ -117,6 +117,27 @@ def test_linked_sub_blocks_f32_row_forms(shape, bc, cases):
 
 
 @pytest.mark.parametrize("dtype", [R.F32, R.F64], ids=["f32", "f64"])
+@pytest.mark.parametrize("layout,w", [(R.SOA, 0), (R.AOS, 0), (R.AOSOA, 16)],
+                         ids=["soa", "aos", "aosoa16"])
+def test_shared_strip_tails(dtype, layout, w):
+    """Wave strips whose short tails share one wave across three
+    consecutive z rows: several groups of rows and a ragged last group, in
+    every layout (the rows' cells then lie up to two planes apart within
+    one wave)."""
+    for shape, bc in (((61, 5, 25), (1, 0, 1)), ((64, 6, 13), (0, 1, 0)),
+                      ((75, 4, 5), (1, 1, 1)), ((130, 5, 11), (0, 0, 1)), ((16, 3, 10), (1, 1, 0))):
+        assert_forms_equal(shape, dtype, layout, w, bc, 2)
+
+
+def test_shared_strip_tails_linked_sub_blocks():
+    """Sub-blocks of 61 cells along x (tails of one cell, three rows to a
+    wave) linked along x, in the strip form and the library's pick, match
+    the whole grid bitwise."""
+    assert_partitions_match((122, 8, 25), R.F64, (1, 0, 1), 5,
+                            (((2, 1, 1), 3), ((2, 1, 1), 0), ((2, 2, 2), 3)))
+
+
+@pytest.mark.parametrize("dtype", [R.F32, R.F64], ids=["f32", "f64"])
 def test_wide_rows_linked_sub_blocks_match_whole_grid(dtype):
     """Rows longer than a workgroup (wave strips), on a whole grid and on
     sub-blocks whose linked x faces fall inside a strip or at its edge:
