@@ -417,8 +417,13 @@ __global__ void __launch_bounds__(256) k_sweep_yz(SweepParams p, const DevGrid* 
 #ifndef RFV_XY_UNROLL_F64
 #define RFV_XY_UNROLL_F64 6
 #endif
-template <typename T> constexpr int xy_unroll() {
-  return sizeof(T) == 4 ? RFV_XY_UNROLL_F32 : RFV_XY_UNROLL_F64;
+// FP32 wave strips loading two rows ahead: 6 rows per trip (a multiple of 2
+// and 3; 12 measured the same)
+#ifndef RFV_XY_UNROLL_WAVES2_F32
+#define RFV_XY_UNROLL_WAVES2_F32 6
+#endif
+template <typename T, int PF> constexpr int xy_unroll() {
+  return sizeof(T) == 8 ? RFV_XY_UNROLL_F64 : (PF == 2 ? RFV_XY_UNROLL_WAVES2_F32 : RFV_XY_UNROLL_F32);
 }
 // Waves per SIMD the wave-strip form is compiled for (caps its registers;
 // the variant that also reduces wave speeds is left uncapped: it needs 163
@@ -432,24 +437,35 @@ template <typename T> constexpr int xy_unroll() {
 template <typename T> constexpr int xy_wave_occupancy() {
   return sizeof(T) == 4 ? RFV_XY_WAVE_OCC_F32 : RFV_XY_WAVE_OCC_F64;
 }
-// Rows loaded ahead of their x sweep (1, 2 or 3).  The wave strips load one
-// row ahead: that frees 10 registers per lane in FP32 (80: six waves per
-// SIMD) and 20 in FP64 (150; 163 with the wave-speed reduction, three waves
-// instead of two), and measured faster: the one-pass planar step at
-// 6400 x 4000 took 0.317 ms against 0.364 with three rows ahead in FP32,
-// 0.539 against 0.569 in FP64; the 1024^3 FP32 step 21.8 ms against 22.5.
+// Rows loaded ahead of their x sweep (1, 2 or 3).  The wave strips that
+// also reduce wave speeds (one-pass planar step) load one row ahead: that
+// frees 10 registers per lane in FP32 and 20 in FP64 (163 with the
+// reduction: three waves per SIMD instead of two), and measured faster: the
+// one-pass planar step at 6400 x 4000 took 0.317 ms against 0.364 with
+// three rows ahead in FP32, 0.539 against 0.569 in FP64.  The 3D strips load
+// two rows ahead, except FP32 strips reading linked x neighbours (one).
+// Against one row ahead: FP64 (164 registers, still three waves per SIMD)
+// 512^3 x-y 2.67 -> 2.61 ms, 256^3 0.362 -> 0.341 ms; FP32 512^3 strips
+// 1.481 -> 1.455 ms, the 64-grid batch in strips 1.119 -> 1.103 ms, but
+// the 2 x 2 x 2 linked sub-blocks of 768^3 5.54 -> 5.58 ms.
 #ifndef RFV_XY_PF_ROWS
 #define RFV_XY_PF_ROWS 3
 #endif
 #ifndef RFV_XY_PF_WAVES_F32
-#define RFV_XY_PF_WAVES_F32 1
+#define RFV_XY_PF_WAVES_F32 2
+#endif
+#ifndef RFV_XY_PF_WAVES_F32_LINKED
+#define RFV_XY_PF_WAVES_F32_LINKED 1
 #endif
 #ifndef RFV_XY_PF_WAVES_F64
-#define RFV_XY_PF_WAVES_F64 1
+#define RFV_XY_PF_WAVES_F64 2
 #endif
-template <typename T, int XM> constexpr int xy_prefetch() {
-  return XM != XM_WAVES ? RFV_XY_PF_ROWS
-                        : (sizeof(T) == 4 ? RFV_XY_PF_WAVES_F32 : RFV_XY_PF_WAVES_F64);
+template <typename T, int XM, bool FUSE, bool LINKX> constexpr int xy_prefetch() {
+  return XM != XM_WAVES   ? RFV_XY_PF_ROWS
+         : FUSE           ? 1
+         : sizeof(T) == 8 ? RFV_XY_PF_WAVES_F64
+         : LINKX          ? RFV_XY_PF_WAVES_F32_LINKED
+                          : RFV_XY_PF_WAVES_F32;
 }
 
 // XM: form of the x exchange (XM_ROWS, XM_WAVES); the forms differ only in
@@ -714,7 +730,7 @@ __global__ void __launch_bounds__(XM == XM_WAVES ? XY_WAVE_THREADS : XY_THREADS)
 
     // raw ring slot of row r: (r - (j0 - 2)) mod PF (rows are loaded PF rows
     // before they are x-swept); x-swept ring slot: (r - (j0 - 2)) mod 3
-    constexpr int PF = xy_prefetch<T, XM>();
+    constexpr int PF = xy_prefetch<T, XM, FUSE, LINKX>();
     T raw[PF][5];
     T xs[3][5];
     T dprev[5], dnext[5], bl[5], br[5], brp[5], fprev[5];
@@ -752,7 +768,7 @@ __global__ void __launch_bounds__(XM == XM_WAVES ? XY_WAVE_THREADS : XY_THREADS)
     // xs[(k+1)%3] (the slot of U_{j-1}), and row j+2+PF is loaded into the
     // raw slot just consumed.  dprev = U_{j+1} - U_j, brp = Ub^R_j,
     // fprev = F_{j-1/2}.
-    constexpr int U = xy_unroll<T>();
+    constexpr int U = xy_unroll<T, PF>();
     static_assert(U % 3 == 0 && U % PF == 0, "the loop must advance the rings by whole periods");
     for (int o0 = 0; o0 < len; o0 += U) {
 #pragma unroll
@@ -1180,7 +1196,6 @@ int xy_mode(int dtype, const ripple_fv_grid* grids, int n, int split_xy) {
   double rows = 0.0, waves = 0.0;
   for (int i = 0; i < n; ++i) {
     const ripple_fv_grid& g = grids[i];
-    const double cells = (double)g.n[0] * g.n[1] * g.n[2];
     const int P = xy_row_lanes(g);
     if (P == 0) return XM_WAVES;
     const int R = XY_THREADS / P;

@@ -50,16 +50,20 @@ template <> struct Arith<float> {
 };
 
 // FP64 reciprocal and square root for the sweeps: the hardware estimates
-// (v_rcp_f64, v_rsq_f64, about 2^-24 relative error) refined by two Newton
-// steps each, which brings them to within about an ulp in 5 and 9
-// instructions, where IEEE division and square root expand to longer
-// sequences.  Positive finite arguments only (the sweeps' densities, sound
-// speeds and wave-speed differences); the time step uses IEEE operations.
+// (v_rcp_f64, v_rsq_f64, relative error e of about 2^-24 or less) refined by
+// one third-order step each, which leaves an error of order e^3 plus the
+// final roundings (about an ulp) in 3 and 5 instructions, where IEEE
+// division and square root expand to longer sequences.  With e = 1 - x r
+// for the reciprocal estimate r, 1/x = r / (1 - e) = r (1 + e + e^2 + ...);
+// with e = 1 - x y^2 for the inverse square root estimate y and s = x y,
+// sqrt(x) = s / sqrt(1 - e) = s (1 + e/2 + 3 e^2/8 + ...).  Positive finite
+// arguments only (the sweeps' densities, sound speeds and wave-speed
+// differences); the time step uses IEEE operations.
 template <> struct Arith<double> {
   static __device__ __forceinline__ double recip(double x) {
-    double r = __builtin_amdgcn_rcp(x);
-    r = __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
-    return __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+    const double r = __builtin_amdgcn_rcp(x);
+    const double e = __builtin_fma(-x, r, 1.0);
+    return __builtin_fma(__builtin_fma(e, e, e), r, r);
   }
   static __device__ __forceinline__ double quot(double a, double b) { return a * recip(b); }
   // 1/a and 1/b from one refined reciprocal of a b (a few ulp; positive a, b
@@ -70,11 +74,10 @@ template <> struct Arith<double> {
     rb = a * r;
   }
   static __device__ __forceinline__ double root(double x) {
-    const double h = 0.5 * x;
-    double y = __builtin_amdgcn_rsq(x);
-    y = __builtin_fma(y, __builtin_fma(-h * y, y, 0.5), y);
-    y = __builtin_fma(y, __builtin_fma(-h * y, y, 0.5), y);
-    return x * y;
+    const double y = __builtin_amdgcn_rsq(x);
+    const double s = x * y;
+    const double e = __builtin_fma(-s, y, 1.0);
+    return __builtin_fma(s, e * __builtin_fma(e, 0.375, 0.5), s);
   }
   static __device__ __forceinline__ double min(double a, double b) { return __builtin_fmin(a, b); }
   static __device__ __forceinline__ double max(double a, double b) { return __builtin_fmax(a, b); }
