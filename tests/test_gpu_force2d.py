@@ -6,7 +6,7 @@ operations) over terms bounded by S_c = max|F_c| + max|G_c| + max|U_c| /
 min(lam) per component; the flux difference adds two faces per axis.  The
 absolute error is therefore bounded by a few tens of ulps of S_c: the tests
 allow 1e-5 S_c in FP32 (about 170 ulps) and 1e-13 S_c in FP64 (about 450
-ulps; FP64 reciprocals are Newton-refined hardware estimates, about an ulp).
+ulps; FP64 reciprocals are refined hardware estimates, about an ulp).
 Inputs the oracle sees are the stored values (FP32 states are first rounded
 to FP32 by the import and read back), so both sides start from the same
 numbers.  Cell-wise random states make every flux difference O(1), which
