@@ -67,6 +67,7 @@ struct PlanCore {
   const ripple_fv_grid* grids = nullptr;  // host descriptors [n]
   bool fused = false;                   // x and y sweeps as one pass
   int seg_xy = 0;                       // rows per tile of the fused pass
+  int seg_z = 0;                        // cells per tile of the z sweep
   int xmode = XM_ROWS;                  // form of the fused pass
   bool planar = false;                  // every grid one cell thick in z: no z sweep
   bool planar_fused = false;            // ... and the x-y pass (wave strips) is the step
@@ -422,7 +423,7 @@ ripple_fv_status validate_batch(ripple_fv_ctx* ctx, int n, const ripple_fv_grid*
 // storage (no allocation): tiles[k] hold n + 1 prefix sums each, halo[k] up
 // to 2 n tasks each, h_grids n descriptors (buffer pointers left null).
 void plan_shape(PlanCore& P, int n, const ripple_fv_grid* grids, int64_t* const tiles[5],
-                HaloTask* const halo[3], DevGrid* h_grids) {
+                HaloTask* const halo[3], DevGrid* h_grids, int cu_count) {
   P.n = n;
   P.dtype = grids[0].dtype;
   P.lay = lay_of(grids[0]);
@@ -456,12 +457,41 @@ void plan_shape(PlanCore& P, int n, const ripple_fv_grid* grids, int64_t* const 
       P.seg_xy = (int)std::max<int64_t>(std::min(16, P.seg_xy),
                                         (int64_t)P.seg_xy * count / XY_MIN_TILES);
   }
+  // The z sweep marches tiles of seg_z cells.  Unless the grids set a
+  // segment, it takes the longest segment (the fewest per column) that
+  // leaves at least Z_MIN_TILES_PER_CU tiles per compute unit (down to
+  // Z_MIN_SEGMENT cells), provided those tiles then all run at once (at most
+  // Z_ROUND_TILES_PER_CU per compute unit: three workgroups of the z sweep
+  // fit a CU in FP32 and FP64); otherwise the library's 128-cell segment.
+  // A tile then re-reads its 4 halo cells over more cells, and the launch
+  // has no partly filled last round.  Measured on the z sweep: 512^3 FP32
+  // 1.115 ms with 128-cell segments (2048 tiles), 1.137 with 256 (1024),
+  // 1.059 with whole columns (512 tiles); 256^3 FP32 0.171 ms with 128 (256
+  // tiles), 0.136 with 64 (512); 256^3 FP64 0.278 ms with 128 (512 tiles),
+  // 0.290 with 64 and with 256; the 64-grid batch 0.937 ms with 128 (2328
+  // tiles), 0.971 with whole columns (1575 tiles: two rounds and a few).
+  P.seg_z = P.tl.yz_segment;
+  if (grids[0].yz_segment == 0) {
+    int nzmax = 1;
+    for (int g = 0; g < n; ++g) nzmax = std::max(nzmax, grids[g].n[2]);
+    for (int parts = 1;; ++parts) {
+      const int seg = (nzmax + parts - 1) / parts;
+      int64_t count = 0;
+      for (int g = 0; g < n; ++g) count += tiles_yz(grids[g], 2, P.tl.yz_block, seg, P.tl.yz_cols);
+      if (count >= (int64_t)Z_MIN_TILES_PER_CU * cu_count || seg <= Z_MIN_SEGMENT) {
+        const bool one_round = count <= (int64_t)Z_ROUND_TILES_PER_CU * cu_count;
+        P.seg_z = one_round ? std::max(seg, std::min(Z_MIN_SEGMENT, nzmax))
+                            : std::min(seg, P.tl.yz_segment);
+        break;
+      }
+    }
+  }
   for (int k = 0; k < 5; ++k) tiles[k][0] = 0;
   for (int g = 0; g < n; ++g) {
     tiles[4][g + 1] = tiles[4][g] + (P.fused || P.planar_fused ? tiles_xy(grids[g], P.seg_xy, P.xmode) : 0);
     tiles[0][g + 1] = tiles[0][g] + tiles_x(grids[g], P.tl.x_block);
     tiles[1][g + 1] = tiles[1][g] + tiles_yz(grids[g], 1, P.tl.yz_block, P.tl.yz_segment, P.tl.yz_cols);
-    tiles[2][g + 1] = tiles[2][g] + tiles_yz(grids[g], 2, P.tl.yz_block, P.tl.yz_segment, P.tl.yz_cols);
+    tiles[2][g + 1] = tiles[2][g] + tiles_yz(grids[g], 2, P.tl.yz_block, P.seg_z, P.tl.yz_cols);
     tiles[3][g + 1] = tiles[3][g] + tiles_ws(grids[g]);
   }
   for (int k = 0; k < 5; ++k) P.tiles[k] = tiles[k];
@@ -524,7 +554,8 @@ void tile_order(const PlanCore& P, int k, std::vector<int32_t>& order) {
     for (int64_t t = P.tiles[k][g]; t < P.tiles[k][g + 1]; ++t) {
       const int64_t lt = t - P.tiles[k][g];
       const int len = k == 4 ? tile_len_xy(G, P.seg_xy, lt)
-                             : tile_len_yz(G, k, P.tl.yz_block, P.tl.yz_segment, P.tl.yz_cols, lt);
+                             : tile_len_yz(G, k, P.tl.yz_block, k == 2 ? P.seg_z : P.tl.yz_segment,
+                                           P.tl.yz_cols, lt);
       cost[(size_t)t] = len + 2 * HALO + 2;
     }
   }
@@ -551,7 +582,7 @@ ripple_fv_status build_plan(ripple_fv_ctx* ctx, int n, const ripple_fv_grid* gri
     halo[k] = P->halo_store[k].data();
   }
   P->h_grid_store.resize(n);
-  plan_shape(*P, n, P->grid_store.data(), tiles, halo, P->h_grid_store.data());
+  plan_shape(*P, n, P->grid_store.data(), tiles, halo, P->h_grid_store.data(), ctx->cu_count);
   for (int k : {1, 2, 4}) {
     if (P->tiles[k][n] == 0) continue;
     tile_order(*P, k, P->order_store[k]);
@@ -699,7 +730,7 @@ ripple_fv_status enqueue_sweep(ripple_fv_ctx* ctx, const PlanCore* P, Launcher& 
   sp.w = P->work(ctx->flag);
   sp.in = in;
   sp.out = out;
-  sp.seg = P->tl.yz_segment;
+  sp.seg = axis == 2 ? P->seg_z : P->tl.yz_segment;
   sp.fuse_s = fuse_s;
   sp.tiles.tile_start = P->d_tiles[axis];
   hipEvent_t e1 = nullptr;
@@ -1177,7 +1208,7 @@ ripple_fv_status ripple_fv_run_batch_noalloc(ripple_fv_ctx* ctx, int32_t n,
   DevGrid hg[NOALLOC_MAX_GRIDS];
   int64_t* tp[5] = {tiles[0], tiles[1], tiles[2], tiles[3], tiles[4]};
   HaloTask* hp[3] = {halo[0], halo[1], halo[2]};
-  plan_shape(P, n, grids, tp, hp, hg);
+  plan_shape(P, n, grids, tp, hp, hg, ctx->cu_count);
   for (int g = 0; g < n; ++g) {
     hg[g].buf[0] = u[g];
     hg[g].buf[1] = work[g];

@@ -443,19 +443,20 @@ template <typename T> constexpr int xy_wave_occupancy() {
 // reduction: three waves per SIMD instead of two), and measured faster: the
 // one-pass planar step at 6400 x 4000 took 0.317 ms against 0.364 with
 // three rows ahead in FP32, 0.539 against 0.569 in FP64.  The 3D strips load
-// two rows ahead, except FP32 strips reading linked x neighbours (one).
-// Against one row ahead: FP64 (164 registers, still three waves per SIMD)
-// 512^3 x-y 2.67 -> 2.61 ms, 256^3 0.362 -> 0.341 ms; FP32 512^3 strips
-// 1.481 -> 1.455 ms, the 64-grid batch in strips 1.119 -> 1.103 ms, but
-// the 2 x 2 x 2 linked sub-blocks of 768^3 5.54 -> 5.58 ms.
+// two rows ahead, except strips reading linked x neighbours (one).  Against
+// one row ahead: FP64 (164 registers, still three waves per SIMD) 512^3 x-y
+// 2.67 -> 2.61 ms, 256^3 0.362 -> 0.341 ms; FP32 512^3 strips 1.481 -> 1.455
+// ms, the 64-grid batch in strips 1.119 -> 1.103 ms, but the 2 x 2 x 2
+// linked sub-blocks of 768^3 5.54 -> 5.58 ms; and the FP64 AoS variant with
+// linked x faces would need more than the 168 registers of three waves.
 #ifndef RFV_XY_PF_ROWS
 #define RFV_XY_PF_ROWS 3
 #endif
 #ifndef RFV_XY_PF_WAVES_F32
 #define RFV_XY_PF_WAVES_F32 2
 #endif
-#ifndef RFV_XY_PF_WAVES_F32_LINKED
-#define RFV_XY_PF_WAVES_F32_LINKED 1
+#ifndef RFV_XY_PF_WAVES_LINKED
+#define RFV_XY_PF_WAVES_LINKED 1
 #endif
 #ifndef RFV_XY_PF_WAVES_F64
 #define RFV_XY_PF_WAVES_F64 2
@@ -463,8 +464,8 @@ template <typename T> constexpr int xy_wave_occupancy() {
 template <typename T, int XM, bool FUSE, bool LINKX> constexpr int xy_prefetch() {
   return XM != XM_WAVES   ? RFV_XY_PF_ROWS
          : FUSE           ? 1
+         : LINKX          ? RFV_XY_PF_WAVES_LINKED
          : sizeof(T) == 8 ? RFV_XY_PF_WAVES_F64
-         : LINKX          ? RFV_XY_PF_WAVES_F32_LINKED
                           : RFV_XY_PF_WAVES_F32;
 }
 

@@ -13,7 +13,7 @@
 //
 // Precision notes.  FP32 uses the hardware reciprocal and square root
 // (v_rcp_f32, v_sqrt_f32, 1 ulp) and v_med3_f32 for minmod; FP64 uses the
-// hardware estimates refined by Newton steps (about an ulp) in the sweeps and
+// hardware estimates refined by a third-order step (about an ulp) in the sweeps and
 // IEEE division and square root for the wave speeds.  Each density is inverted once per state and
 // velocities and kinetic energy are formed by multiplication.  The build
 // disables implicit contraction; fused multiply-adds appear only where written
