@@ -216,12 +216,25 @@ __global__ void __launch_bounds__(NT) k_sweep_x(SweepParams p, const DevGrid* __
 #ifndef RFV_YZ_ORDER
 #define RFV_YZ_ORDER 0
 #endif
+// Cache policy of the z sweep's loads and stores: non-temporal (2, the
+// buffer instructions' nt bit).  Each cell is read and written once and no
+// other tile reads it in the same launch (but for the 4 halo cells of a
+// segment).  Measured at 512^3 against the default policy: FP32 z sweep
+// 1.050 -> 1.017 ms, FP64 2.234 -> 2.207 ms.  The y sweep keeps the default.
+#ifndef RFV_Z_LOAD_POLICY
+#define RFV_Z_LOAD_POLICY 2
+#endif
+#ifndef RFV_Z_STORE_POLICY
+#define RFV_Z_STORE_POLICY 2
+#endif
 template <typename T, int LAY, int D, bool FUSE, int COLS>
 __global__ void __launch_bounds__(256) k_sweep_yz(SweepParams p, const DevGrid* __restrict__ grids,
                                                   const int64_t* __restrict__ tile_start,
                                                   const double* __restrict__ lamv) {
   constexpr int K = RFV_YZ_RING;  // ring slots
   static_assert(K >= 4, "ring must hold the stencil and one cell ahead");
+  constexpr int LDP = D == 2 ? RFV_Z_LOAD_POLICY : LD_POL;
+  constexpr int STP = D == 2 ? RFV_Z_STORE_POLICY : ST_POL;
   __shared__ T red[3 * 16];
   const int nt = blockDim.x;
   const int tid = threadIdx.x;
@@ -279,7 +292,7 @@ __global__ void __launch_bounds__(256) k_sweep_yz(SweepParams p, const DevGrid* 
     T ring[K][COLS][5];
     T dprev[COLS][5], dnext[5], bl[5], br[COLS][5], brp[COLS][5], fprev[COLS][5];
 #pragma unroll
-    for (int k = 0; k < K; ++k) load_group<T, LAY, COLS>(src, row(j0 - 2 + k), ptot, lane, ring[k]);
+    for (int k = 0; k < K; ++k) load_group<T, LAY, COLS, LDP>(src, row(j0 - 2 + k), ptot, lane, ring[k]);
 #pragma unroll
     for (int m = 0; m < COLS; ++m) {
 #pragma unroll
@@ -301,7 +314,7 @@ __global__ void __launch_bounds__(256) k_sweep_yz(SweepParams p, const DevGrid* 
         dprev[m][c] = dnext[c];
       }
     }
-    load_group<T, LAY, COLS>(src, row(j0 + K - 2), ptot, lane, ring[0]);
+    load_group<T, LAY, COLS, LDP>(src, row(j0 + K - 2), ptot, lane, ring[0]);
 
     T smax[3] = {T(0), T(0), T(0)};
     bool bad = false;
@@ -314,7 +327,7 @@ __global__ void __launch_bounds__(256) k_sweep_yz(SweepParams p, const DevGrid* 
         const int o = o0 + k;
         if (o >= len) break;
         const int j = j0 + o;
-        load_group<T, LAY, COLS>(src, row(j + K - 1), ptot, lane, ring[(k + 1) % K]);
+        load_group<T, LAY, COLS, LDP>(src, row(j + K - 1), ptot, lane, ring[(k + 1) % K]);
         T out[COLS][5];
 #pragma unroll
         for (int m = 0; m < COLS; ++m) {
@@ -335,7 +348,7 @@ __global__ void __launch_bounds__(256) k_sweep_yz(SweepParams p, const DevGrid* 
           }
         }
         if (act[0])
-          store_group<T, LAY, COLS>(dst, q0 + (int64_t)(j + 2) * stride, ptot, lane, out, act);
+          store_group<T, LAY, COLS, STP>(dst, q0 + (int64_t)(j + 2) * stride, ptot, lane, out, act);
         if (FUSE) {
 #pragma unroll
           for (int m = 0; m < COLS; ++m) {
@@ -467,6 +480,16 @@ template <typename T, int XM, bool FUSE, bool LINKX> constexpr int xy_prefetch()
          : LINKX          ? RFV_XY_PF_WAVES_LINKED
          : sizeof(T) == 8 ? RFV_XY_PF_WAVES_F64
                           : RFV_XY_PF_WAVES_F32;
+}
+
+// Cache policy of the fused pass's stores: non-temporal (2) for the FP32
+// rows form (512^3: 1.306 -> 1.283 ms), the default elsewhere (FP64 strips
+// 2.609 -> 2.660 ms with non-temporal stores).
+#ifndef RFV_XY_ROWS_STORE_POLICY_F32
+#define RFV_XY_ROWS_STORE_POLICY_F32 2
+#endif
+template <typename T, int XM> constexpr int xy_store_policy() {
+  return XM == XM_ROWS && sizeof(T) == 4 ? RFV_XY_ROWS_STORE_POLICY_F32 : ST_POL;
 }
 
 // XM: form of the x exchange (XM_ROWS, XM_WAVES); the forms differ only in
@@ -794,7 +817,7 @@ __global__ void __launch_bounds__(XM == XM_WAVES ? XY_WAVE_THREADS : XY_THREADS)
           brp[c] = br[c];
           dprev[c] = dnext[c];
         }
-        if (on) store_cell_rel<T, LAY>(dst, q0 + (int64_t)(j + 2) * G.px, ptot, lane_st, out);
+        if (on) store_cell_rel<T, LAY, xy_store_policy<T, XM>()>(dst, q0 + (int64_t)(j + 2) * G.px, ptot, lane_st, out);
         if constexpr (FUSE) {
           T sc[3];
           bool b_ = false;

@@ -82,59 +82,59 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void* base) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, BUFFER_RECORDS, BUFFER_DWORD3);
 }
 
-template <typename T>
+template <typename T, int POL = LD_POL>
 __device__ __forceinline__ T gload(const void* base, uint32_t lane_bytes) {
   if constexpr (sizeof(T) == 4) {
-    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rsrc(base), (int)lane_bytes, 0, LD_POL));
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rsrc(base), (int)lane_bytes, 0, POL));
   } else {
-    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rsrc(base), (int)lane_bytes, 0, LD_POL));
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rsrc(base), (int)lane_bytes, 0, POL));
   }
 }
 
-template <typename T>
+template <typename T, int POL = ST_POL>
 __device__ __forceinline__ void gstore(void* base, uint32_t lane_bytes, T v) {
   if constexpr (sizeof(T) == 4) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), rsrc(base), (int)lane_bytes, 0, ST_POL);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), rsrc(base), (int)lane_bytes, 0, POL);
   } else {
     using u2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(rsrc(base), 0, 0, 0));
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), rsrc(base), (int)lane_bytes, 0, ST_POL);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), rsrc(base), (int)lane_bytes, 0, POL);
   }
 }
 
 // N consecutive elements of T at base + lane_bytes, as one buffer access of
 // 4, 8 or 16 bytes.
-template <typename T, int N>
+template <typename T, int N, int POL = LD_POL>
 __device__ __forceinline__ void gload_n(const void* base, uint32_t lane_bytes, T out[N]) {
   constexpr int B = (int)sizeof(T) * N;
   static_assert(B == 4 || B == 8 || B == 16, "unsupported access width");
   if constexpr (B == 4) {
-    const uint32_t v = __builtin_amdgcn_raw_buffer_load_b32(rsrc(base), (int)lane_bytes, 0, LD_POL);
+    const uint32_t v = __builtin_amdgcn_raw_buffer_load_b32(rsrc(base), (int)lane_bytes, 0, POL);
     __builtin_memcpy(out, &v, B);
   } else if constexpr (B == 8) {
-    const auto v = __builtin_amdgcn_raw_buffer_load_b64(rsrc(base), (int)lane_bytes, 0, LD_POL);
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(rsrc(base), (int)lane_bytes, 0, POL);
     __builtin_memcpy(out, &v, B);
   } else {
-    const auto v = __builtin_amdgcn_raw_buffer_load_b128(rsrc(base), (int)lane_bytes, 0, LD_POL);
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(rsrc(base), (int)lane_bytes, 0, POL);
     __builtin_memcpy(out, &v, B);
   }
 }
 
-template <typename T, int N>
+template <typename T, int N, int POL = ST_POL>
 __device__ __forceinline__ void gstore_n(void* base, uint32_t lane_bytes, const T in[N]) {
   constexpr int B = (int)sizeof(T) * N;
   static_assert(B == 4 || B == 8 || B == 16, "unsupported access width");
   if constexpr (B == 4) {
     uint32_t v;
     __builtin_memcpy(&v, in, B);
-    __builtin_amdgcn_raw_buffer_store_b32(v, rsrc(base), (int)lane_bytes, 0, ST_POL);
+    __builtin_amdgcn_raw_buffer_store_b32(v, rsrc(base), (int)lane_bytes, 0, POL);
   } else if constexpr (B == 8) {
     decltype(__builtin_amdgcn_raw_buffer_load_b64(rsrc(base), 0, 0, 0)) v;
     __builtin_memcpy(&v, in, B);
-    __builtin_amdgcn_raw_buffer_store_b64(v, rsrc(base), (int)lane_bytes, 0, ST_POL);
+    __builtin_amdgcn_raw_buffer_store_b64(v, rsrc(base), (int)lane_bytes, 0, POL);
   } else {
     decltype(__builtin_amdgcn_raw_buffer_load_b128(rsrc(base), 0, 0, 0)) v;
     __builtin_memcpy(&v, in, B);
-    __builtin_amdgcn_raw_buffer_store_b128(v, rsrc(base), (int)lane_bytes, 0, ST_POL);
+    __builtin_amdgcn_raw_buffer_store_b128(v, rsrc(base), (int)lane_bytes, 0, POL);
   }
 }
 
@@ -144,34 +144,34 @@ __device__ __forceinline__ const void* comp_base(const void* buf, int64_t q0, in
   return static_cast<const T*>(buf) + Layout<LAY>::off(q0, c, ptot);
 }
 
-template <typename T, int LAY>
+template <typename T, int LAY, int POL = LD_POL>
 __device__ __forceinline__ void load_cell_rel(const void* buf, int64_t q0, int64_t ptot,
                                               uint32_t lane_bytes, T u[5]) {
   if constexpr (LAY == LAY_AOS && sizeof(T) == 8) {
     // a 40-byte FP64 cell (8-byte aligned) as 16 + 16 + 8 bytes: three
     // accesses per lane instead of five
     const void* b = comp_base<T, LAY>(buf, q0, 0, ptot);
-    gload_n<T, 2>(b, lane_bytes, u);
-    gload_n<T, 2>(b, lane_bytes + 16u, u + 2);
-    u[4] = gload<T>(b, lane_bytes + 32u);
+    gload_n<T, 2, POL>(b, lane_bytes, u);
+    gload_n<T, 2, POL>(b, lane_bytes + 16u, u + 2);
+    u[4] = gload<T, POL>(b, lane_bytes + 32u);
   } else {
 #pragma unroll
-    for (int c = 0; c < 5; ++c) u[c] = gload<T>(comp_base<T, LAY>(buf, q0, c, ptot), lane_bytes);
+    for (int c = 0; c < 5; ++c) u[c] = gload<T, POL>(comp_base<T, LAY>(buf, q0, c, ptot), lane_bytes);
   }
 }
 
-template <typename T, int LAY>
+template <typename T, int LAY, int POL = ST_POL>
 __device__ __forceinline__ void store_cell_rel(void* buf, int64_t q0, int64_t ptot,
                                                uint32_t lane_bytes, const T u[5]) {
   if constexpr (LAY == LAY_AOS && sizeof(T) == 8) {
     void* b = const_cast<void*>(comp_base<T, LAY>(buf, q0, 0, ptot));
-    gstore_n<T, 2>(b, lane_bytes, u);
-    gstore_n<T, 2>(b, lane_bytes + 16u, u + 2);
-    gstore<T>(b, lane_bytes + 32u, u[4]);
+    gstore_n<T, 2, POL>(b, lane_bytes, u);
+    gstore_n<T, 2, POL>(b, lane_bytes + 16u, u + 2);
+    gstore<T, POL>(b, lane_bytes + 32u, u[4]);
   } else {
 #pragma unroll
     for (int c = 0; c < 5; ++c)
-      gstore<T>(const_cast<void*>(comp_base<T, LAY>(buf, q0, c, ptot)), lane_bytes, u[c]);
+      gstore<T, POL>(const_cast<void*>(comp_base<T, LAY>(buf, q0, c, ptot)), lane_bytes, u[c]);
   }
 }
 
@@ -179,20 +179,20 @@ __device__ __forceinline__ void store_cell_rel(void* buf, int64_t q0, int64_t pt
 // u[k][c] is component c of cell k.  In SoA and AoSoA the COLS values of one
 // component are adjacent in memory and move as one wider access; in AoS each
 // cell is read on its own.
-template <typename T, int LAY, int COLS>
+template <typename T, int LAY, int COLS, int POL = LD_POL>
 __device__ __forceinline__ void load_group(const void* buf, int64_t q0, int64_t ptot,
                                            uint32_t lane_bytes, T u[COLS][5]) {
   if constexpr (COLS == 1) {
-    load_cell_rel<T, LAY>(buf, q0, ptot, lane_bytes, u[0]);
+    load_cell_rel<T, LAY, POL>(buf, q0, ptot, lane_bytes, u[0]);
   } else if constexpr (LAY == LAY_AOS) {
 #pragma unroll
     for (int k = 0; k < COLS; ++k)
-      load_cell_rel<T, LAY>(buf, q0, ptot, lane_bytes + (uint32_t)(5 * k * sizeof(T)), u[k]);
+      load_cell_rel<T, LAY, POL>(buf, q0, ptot, lane_bytes + (uint32_t)(5 * k * sizeof(T)), u[k]);
   } else {
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
       T v[COLS];
-      gload_n<T, COLS>(comp_base<T, LAY>(buf, q0, c, ptot), lane_bytes, v);
+      gload_n<T, COLS, POL>(comp_base<T, LAY>(buf, q0, c, ptot), lane_bytes, v);
 #pragma unroll
       for (int k = 0; k < COLS; ++k) u[k][c] = v[k];
     }
@@ -202,17 +202,17 @@ __device__ __forceinline__ void load_group(const void* buf, int64_t q0, int64_t 
 // Store of a group: act[k] says whether cell k lies inside the row.  A
 // whole group moves as one wider access per component (SoA, AoSoA); the
 // group that straddles the end of a row stores its cells one by one.
-template <typename T, int LAY, int COLS>
+template <typename T, int LAY, int COLS, int POL = ST_POL>
 __device__ __forceinline__ void store_group(void* buf, int64_t q0, int64_t ptot,
                                             uint32_t lane_bytes, const T u[COLS][5],
                                             const bool act[COLS]) {
   if constexpr (COLS == 1) {
-    store_cell_rel<T, LAY>(buf, q0, ptot, lane_bytes, u[0]);
+    store_cell_rel<T, LAY, POL>(buf, q0, ptot, lane_bytes, u[0]);
   } else if constexpr (LAY == LAY_AOS) {
 #pragma unroll
     for (int k = 0; k < COLS; ++k)
       if (act[k])
-        store_cell_rel<T, LAY>(buf, q0, ptot, lane_bytes + (uint32_t)(5 * k * sizeof(T)), u[k]);
+        store_cell_rel<T, LAY, POL>(buf, q0, ptot, lane_bytes + (uint32_t)(5 * k * sizeof(T)), u[k]);
   } else {
     if (act[COLS - 1]) {
 #pragma unroll
@@ -220,13 +220,13 @@ __device__ __forceinline__ void store_group(void* buf, int64_t q0, int64_t ptot,
         T v[COLS];
 #pragma unroll
         for (int k = 0; k < COLS; ++k) v[k] = u[k][c];
-        gstore_n<T, COLS>(const_cast<void*>(comp_base<T, LAY>(buf, q0, c, ptot)), lane_bytes, v);
+        gstore_n<T, COLS, POL>(const_cast<void*>(comp_base<T, LAY>(buf, q0, c, ptot)), lane_bytes, v);
       }
     } else {
 #pragma unroll
       for (int k = 0; k < COLS - 1; ++k)
         if (act[k])
-          store_cell_rel<T, LAY>(buf, q0, ptot, lane_bytes + (uint32_t)(k * sizeof(T)), u[k]);
+          store_cell_rel<T, LAY, POL>(buf, q0, ptot, lane_bytes + (uint32_t)(k * sizeof(T)), u[k]);
     }
   }
 }
