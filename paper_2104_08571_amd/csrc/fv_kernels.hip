@@ -216,11 +216,14 @@ __global__ void __launch_bounds__(NT) k_sweep_x(SweepParams p, const DevGrid* __
 #ifndef RFV_YZ_ORDER
 #define RFV_YZ_ORDER 0
 #endif
-// Cache policy of the z sweep's loads and stores: non-temporal (2, the
-// buffer instructions' nt bit).  Each cell is read and written once and no
-// other tile reads it in the same launch (but for the 4 halo cells of a
-// segment).  Measured at 512^3 against the default policy: FP32 z sweep
-// 1.050 -> 1.017 ms, FP64 2.234 -> 2.207 ms.  The y sweep keeps the default.
+// Cache policy of the z sweep's loads and stores in SoA and AoSoA:
+// non-temporal (2, the buffer instructions' nt bit).  Each cell is read and
+// written once and no other tile reads it in the same launch (but for the 4
+// halo cells of a segment).  Measured against the default policy: 512^3
+// FP32 z sweep 1.047 -> 1.014 ms, FP64 2.234 -> 2.216 ms; 256^3 FP64 0.275
+// -> 0.265 ms; the 64-grid batch 0.941 -> 0.856 ms.  AoS (whose lanes' 40-
+// or 20-byte cells share lines) and the y sweep keep the default: the 256^3
+// FP64 AoS z sweep took 0.404 ms against 0.329.
 #ifndef RFV_Z_LOAD_POLICY
 #define RFV_Z_LOAD_POLICY 2
 #endif
@@ -233,8 +236,9 @@ __global__ void __launch_bounds__(256) k_sweep_yz(SweepParams p, const DevGrid* 
                                                   const double* __restrict__ lamv) {
   constexpr int K = RFV_YZ_RING;  // ring slots
   static_assert(K >= 4, "ring must hold the stencil and one cell ahead");
-  constexpr int LDP = D == 2 ? RFV_Z_LOAD_POLICY : LD_POL;
-  constexpr int STP = D == 2 ? RFV_Z_STORE_POLICY : ST_POL;
+  constexpr bool NTZ = D == 2 && LAY != LAY_AOS;
+  constexpr int LDP = NTZ ? RFV_Z_LOAD_POLICY : LD_POL;
+  constexpr int STP = NTZ ? RFV_Z_STORE_POLICY : ST_POL;
   __shared__ T red[3 * 16];
   const int nt = blockDim.x;
   const int tid = threadIdx.x;
