@@ -115,7 +115,11 @@ enum ripple_fv_kernel_kind {
  *           change results.
  *           x_block: threads per workgroup of the x sweep (128, 256);
  *           yz_block: threads per workgroup of the y/z sweeps (64, 128, 256);
- *           yz_segment: cells each y/z thread advances (>= 4; 0 = 128);
+ *           yz_segment: cells each y/z thread advances (>= 4; 0 = 128 for
+ *           the y sweep and the fused x-y pass, which shortens it on thin
+ *           batches; the z sweep then takes the longest segment that still
+ *           gives two tiles per compute unit if all its tiles then run at
+ *           once, else 128);
  *           persist: workgroups per CU of persistent launches (0 = one per tile);
  *           yz_cols: adjacent x cells per thread of the separate y and z
  *           sweeps (1, 2, 4; 0 = 2 for FP32 SoA/AoSoA, else 1); FP32 AoS
