@@ -460,16 +460,18 @@ void plan_shape(PlanCore& P, int n, const ripple_fv_grid* grids, int64_t* const 
   // The z sweep marches tiles of seg_z cells.  Unless the grids set a
   // segment, it takes the longest segment (the fewest per column) that
   // leaves at least Z_MIN_TILES_PER_CU tiles per compute unit (down to
-  // Z_MIN_SEGMENT cells), provided those tiles then all run at once (at most
-  // Z_ROUND_TILES_PER_CU per compute unit: three workgroups of the z sweep
-  // fit a CU in FP32 and FP64); otherwise the library's 128-cell segment.
-  // A tile then re-reads its 4 halo cells over more cells, and the launch
-  // has no partly filled last round.  Measured on the z sweep: 512^3 FP32
-  // 1.115 ms with 128-cell segments (2048 tiles), 1.137 with 256 (1024),
-  // 1.059 with whole columns (512 tiles); 256^3 FP32 0.171 ms with 128 (256
-  // tiles), 0.136 with 64 (512); 256^3 FP64 0.278 ms with 128 (512 tiles),
-  // 0.290 with 64 and with 256; the 64-grid batch 0.937 ms with 128 (2328
-  // tiles), 0.971 with whole columns (1575 tiles: two rounds and a few).
+  // Z_MIN_SEGMENT cells), provided those tiles then take about one round (at
+  // most Z_ROUND_TILES_PER_CU per compute unit; three workgroups of the z
+  // sweep fit a CU in FP32 and FP64); otherwise the library's 128-cell
+  // segment.  A tile then re-reads its 4 halo cells over more cells, and the
+  // launch has no long, partly filled last round.  Measured on the z sweep:
+  // 512^3 FP32 1.115 ms with 128-cell segments (2048 tiles), 1.137 with 256
+  // (1024), 1.059 with whole columns (512 tiles); 512^3 FP64 2.23-2.24 ms
+  // with 128, 2.157 with whole columns (1024 tiles); 256^3 FP32 0.171 ms
+  // with 128 (256 tiles), 0.136 with 64 (512); 256^3 FP64 0.278 ms with 128
+  // (512 tiles), 0.290 with 64 and with 256; the 64-grid batch 0.937 ms with
+  // 128 (2328 tiles), 0.971 with whole columns (1575 tiles: two rounds and a
+  // few).
   P.seg_z = P.tl.yz_segment;
   if (grids[0].yz_segment == 0) {
     int nzmax = 1;

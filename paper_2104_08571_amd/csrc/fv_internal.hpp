@@ -105,7 +105,7 @@ constexpr int XY_WAVE_CELLS = 60;
 constexpr int XY_WAVE_THREADS = 256;   // workgroup of the wave-strip form
 constexpr int64_t XY_MIN_TILES = 2048;
 constexpr int Z_MIN_TILES_PER_CU = 2;   // z sweep: segments as long as this allows
-constexpr int Z_ROUND_TILES_PER_CU = 3; // ... while every tile runs at once
+constexpr int Z_ROUND_TILES_PER_CU = 4; // ... while the tiles take about one round
 constexpr int Z_MIN_SEGMENT = 16;
 bool xy_eligible(const ripple_fv_grid& g);
 // Form of the fused pass for a batch of grids of precision dtype and the
