@@ -118,8 +118,8 @@ enum ripple_fv_kernel_kind {
  *           yz_segment: cells each y/z thread advances (>= 4; 0 = 128 for
  *           the y sweep and the fused x-y pass, which shortens it on thin
  *           batches; the z sweep then takes the longest segment that still
- *           gives two tiles per compute unit if all its tiles then run at
- *           once, else 128);
+ *           gives two tiles per compute unit if there are then at most
+ *           four per compute unit, about one round, else 128);
  *           persist: workgroups per CU of persistent launches (0 = one per tile);
  *           yz_cols: adjacent x cells per thread of the separate y and z
  *           sweeps (1, 2, 4; 0 = 2 for FP32 SoA/AoSoA, else 1); FP32 AoS
